@@ -1,0 +1,161 @@
+"""Scale exponents log2(mu_i), log2(nu_j) (test infrastructure only).
+
+* ``norm_sq_ru``       the squared 2-norm "computed with rounding-up"
+                       (Algorithms 1 and 2, Section 4)
+* ``alg2_log2_mu``     Algorithm 2, the proposed scaling (Section 4)
+* ``alg1_log2_mu``     Algorithm 1, the original fast mode (Section 2.3)
+* ``accurate_log2``    accurate mode (Section 2.3)
+
+Every rounding is done exactly on rationals (``oracle.fp``).
+
+Readings taken where the paper leaves a choice open:
+
+* Summation order of the rounded-up sum of squares (not fixed by the paper;
+  every order gives an upper bound).  The oracle uses one fixed order,
+  ``KC``-element chunks: each chunk's squares are added left to right, then
+  the chunk sums are added left to right, every square and every addition
+  rounded toward +inf in binary64.  Binary64 (not binary32) is used because
+  binary32 squares overflow or underflow for inputs scaled by 2**+-300.
+* The binary64 quantity a_norm / 2**s in [1, 2) is converted to binary32 for
+  the logarithm by rounding up, which can only make the bound more
+  conservative.
+* The fast log2 is the correctly rounded binary32 log2 (``fp.log2_rn32``).
+* A row (or column) whose squared norm is 0 gets exponent 0: log2(0) is
+  undefined, and every entry of the integer row is 0 whatever the scale.
+* floor(w - t) in Algorithm 2 is taken on the exact difference of the two
+  binary32 values.
+* Algorithm 1 evaluates single_up(delta * (log2f(.) + s)) as two rounded
+  binary32 operations: the sum rounded up, then the product rounded up.
+* Accurate mode: the paper writes mu_i = mu'^{-1}_i * 2^(...), which does not
+  satisfy the bound its own proof derives; the proof needs
+  mu_i = mu'_i * 2^(...), which is what is implemented.  The binary32
+  product delta * tilde-log2(.) is rounded up.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+
+from . import fp
+
+KC = 64  # chunk length of the fixed summation order
+
+
+def norm_sq_ru(v, kc: int = KC) -> float:
+    """sum(v_h**2) with every square and addition rounded toward +inf.
+
+    Order: chunks of ``kc`` consecutive entries; inside a chunk left to right;
+    then the chunk sums left to right.  Returns a binary64 value (inf if the
+    sum overflows, NaN if an entry is NaN).
+    """
+    v = [float(x) for x in np.asarray(v, dtype=np.float64).ravel()]
+    partials = []
+    for c0 in range(0, len(v), kc):
+        part = 0.0
+        for a in v[c0:c0 + kc]:
+            part = fp.ru_add(part, fp.ru_square(a))
+        partials.append(part)
+    total = 0.0
+    for part in partials:
+        total = fp.ru_add(total, part)
+    return total
+
+
+def _split_pow2(S: float):
+    """s = floor(log2 S) and the exact ratio S / 2**s in [1, 2)."""
+    x = Fraction(S)
+    s = fp.floor_log2(x)
+    return s, x / fp._pow2(s)
+
+
+def alg2_log2_mu(S: float, p_prop: Fraction) -> int:
+    """Algorithm 2 (Section 4): log2(mu_i) from the rounded-up squared norm.
+
+        s = floor(log2(a_norm))
+        t = single_up(0.5 * log2f(a_norm / 2**s) + 2 u32)
+        w = single_down(P'_prop - 0.5 s)
+        return floor(w - t)
+    """
+    if not math.isfinite(S):
+        raise OverflowError("non-finite squared norm")
+    if S == 0.0:
+        return 0
+    s, x = _split_pow2(S)
+    L = fp.log2_rn32(fp.ru32(x))
+    t = fp.ru32(L / 2 + 2 * fp.U32)
+    w = fp.rd32(Fraction(p_prop) - Fraction(s, 2))
+    return math.floor(w - t)
+
+
+def alg1_log2_mu(S: float, amax: float, p_fast: Fraction, delta: Fraction) -> int:
+    """Algorithm 1 (Section 2.3): log2(mu_i) in the original fast mode.
+
+        s = floor(log2(a_norm))
+        t = single_up(delta * (log2f(a_norm / 2**s) + s))
+        return floor(P'_fast - max(1, t)) - floor(log2(a_max))
+    """
+    if not math.isfinite(S):
+        raise OverflowError("non-finite squared norm")
+    if S == 0.0:
+        return 0
+    s, x = _split_pow2(S)
+    L = fp.log2_rn32(fp.ru32(x))
+    t = fp.ru32(Fraction(delta) * fp.ru32(L + s))
+    return math.floor(Fraction(p_fast) - max(Fraction(1), t)) - fp.floor_log2(Fraction(amax))
+
+
+def tilde_log2_ru(x: int) -> Fraction:
+    """tilde-log2 of eq. (flog2), Section 2.3, for an integer x > 0:
+    single_up(log2f(x / 2**floor(log2 x)) + floor(log2 x))."""
+    e = fp.floor_log2(Fraction(x))
+    L = fp.log2_rn32(fp.ru32(Fraction(x) / fp._pow2(e)))
+    return fp.ru32(L + e)
+
+
+def accurate_log2(A, B, p_accu: Fraction, delta: Fraction):
+    """Accurate mode (Section 2.3): returns (log2 mu, log2 nu, Abar, Bbar, Cbar).
+
+    mu'_i = 2**(5 - floor(log2 max_h |a_ih|)), Abar = ceil(mu' |A|) <= 64,
+    Cbar = Abar Bbar (an exact integer product), and
+    log2 mu_i = log2 mu'_i + floor(P'_accu - delta * tilde-log2(max_h cbar_ih)),
+    likewise for nu_j with column maxima of Cbar.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    m, k = A.shape
+    n = B.shape[1]
+
+    def first_scale(rows):
+        out = []
+        for r in rows:
+            amax = float(np.max(np.abs(r))) if r.size else 0.0
+            out.append(None if amax == 0.0 else 5 - fp.floor_log2(Fraction(amax)))
+        return out
+
+    ea = first_scale(A)
+    eb = first_scale(B.T)
+
+    def ceil_scaled(x: float, e):
+        if e is None:
+            return 0
+        v = Fraction(abs(x)) * fp._pow2(e)
+        return -((-v.numerator) // v.denominator)
+
+    Abar = np.array([[ceil_scaled(A[i, h], ea[i]) for h in range(k)] for i in range(m)],
+                    dtype=np.int64).reshape(m, k)
+    Bbar = np.array([[ceil_scaled(B[h, j], eb[j]) for j in range(n)] for h in range(k)],
+                    dtype=np.int64).reshape(k, n)
+    assert Abar.size == 0 or Abar.max() <= 127
+    Cbar = Abar @ Bbar
+
+    def final(e1, cmax):
+        if e1 is None or cmax == 0:
+            return 0
+        corr = fp.ru32(Fraction(delta) * tilde_log2_ru(int(cmax)))
+        return e1 + math.floor(Fraction(p_accu) - corr)
+
+    emu = [final(ea[i], int(Cbar[i, :].max()) if n else 0) for i in range(m)]
+    enu = [final(eb[j], int(Cbar[:, j].max()) if m else 0) for j in range(n)]
+    return emu, enu, Abar, Bbar, Cbar
