@@ -1,0 +1,192 @@
+/*
+ * ozaki2.h -- C ABI of libozaki2: FP64 (and FP32) matrix multiplication
+ * emulated with INT8 matrix cores by Ozaki scheme II, fast mode with the
+ * scale-invariant scaling of Kawakami & Takahashi, "Improved Scaling for Fast
+ * Mode of Ozaki Scheme II" (Section 4, Algorithm 2), on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The product C ~ A B is computed in the four steps of Section 2.2:
+ *   1. moduli p_1..p_N (the first N of the list printed in Section 3.1),
+ *      P = prod p_t, P_t = P / p_t, q_t = P_t^-1 mod p_t;
+ *   2. A' = trunc(diag(mu) A), B' = trunc(B diag(nu)) with mu_i, nu_j powers
+ *      of two chosen so that 2 sum_h |a'_ih| |b'_hj| < P (eq. os2-condition);
+ *   3. the N products rmod(A', p_t) rmod(B', p_t) on INT8 MFMA with INT32
+ *      accumulation, combined by the CRT (Theorem 1) into C'' = A'B';
+ *   4. C = diag(mu)^-1 C'' diag(nu)^-1, rounded once to the output format.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major (BLAS): element (i, j) of a matrix with
+ *   leading dimension ld is at index i + j * ld.
+ * - A, B and C are DEVICE pointers owned by the caller.  The library reads
+ *   A and B, writes C(0:m-1, 0:n-1) only, and never touches padding rows of
+ *   C (i >= m).  C must not overlap A or B.
+ * - All GPU work is enqueued on the library's current stream (see
+ *   ozaki2_set_stream) and the call returns without waiting for it.
+ * - Return value: 0 on success; -i if argument i (1-based) is invalid, in
+ *   the style of BLAS xerbla; a positive OZ2_ERR_* code otherwise.  On any
+ *   error nothing is launched and C is untouched.  No exception crosses the
+ *   ABI.
+ * - Not thread-safe: one host thread drives the library at a time.
+ */
+#ifndef OZAKI2_H
+#define OZAKI2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Scaling modes (how mu and nu of Step 2 are chosen). */
+#define OZ2_MODE_REVISED  0 /* Section 4, Algorithm 2: the proposed scaling */
+#define OZ2_MODE_ORIGINAL 1 /* Section 2.3, Algorithm 1: original fast mode */
+#define OZ2_MODE_ACCURATE 2 /* Section 2.3: accurate mode (extra INT8 GEMM) */
+
+/* Status codes (positive; argument errors are negative). */
+#define OZ2_SUCCESS          0
+#define OZ2_ERR_K_TOO_LARGE  1 /* k > 2^17: INT32 accumulation could overflow
+                                  (Section 2.2); blocking is not implemented */
+#define OZ2_ERR_WORKSPACE    2 /* workspace allocation failed */
+#define OZ2_ERR_HIP          3 /* a HIP runtime call failed */
+#define OZ2_ERR_UNSUPPORTED  4 /* valid request this build does not support */
+#define OZ2_ERR_TOO_LARGE    5 /* a size overflows the library's indexing */
+
+/* Device status bits reported by ozaki2_get_device_status. */
+#define OZ2_STATUS_NONFINITE 1 /* a row/column had a NaN/Inf entry or a squared
+                                  norm that overflowed binary64; its output
+                                  row/column was written as NaN */
+
+/* Limits. */
+#define OZ2_N_MIN 2
+#define OZ2_N_MAX 20
+#define OZ2_K_MAX 131072 /* 2^17 */
+
+/*
+ * ozaki2_dgemm -- C ~ A B for binary64 A (m x k, lda) and B (k x n, ldb);
+ * C (m x n, ldc) is binary64.
+ *
+ *   m, n, k   >= 0 (args 1-3); k <= OZ2_K_MAX.
+ *   A, lda    device pointer, lda >= max(1, m) (args 4-5).
+ *   B, ldb    device pointer, ldb >= max(1, k) (args 6-7).
+ *   C, ldc    device pointer, ldc >= max(1, m) (args 8-9).
+ *   N         number of moduli, OZ2_N_MIN..OZ2_N_MAX (arg 10).
+ *   mode      OZ2_MODE_* (arg 11).
+ *
+ * Null pointers are accepted only when the matrix has no elements.  m or n
+ * equal to 0 is a quick return; k = 0 writes C = 0.  Each element of C is
+ * the single correctly rounded (nearest-even) value of C''_ij * 2^-(e_i+f_j),
+ * where C'' = A'B' is exact (Section 2.2, Step 4).
+ *
+ * Workspace: device memory set by ozaki2_set_workspace is used if it is
+ * large enough (ozaki2_workspace_size); otherwise the library allocates its
+ * own (hipMalloc, kept and grown on demand, freed by ozaki2_finalize).
+ */
+int ozaki2_dgemm(int64_t m, int64_t n, int64_t k,
+                 const double* A, int64_t lda,
+                 const double* B, int64_t ldb,
+                 double* C, int64_t ldc,
+                 int N, int mode);
+
+/*
+ * ozaki2_sgemm -- as ozaki2_dgemm for binary32 A, B and C (Section 5 applies
+ * the same scheme to SGEMM).  Squared norms are still summed in binary64
+ * with rounding up; C is rounded once to binary32.
+ */
+int ozaki2_sgemm(int64_t m, int64_t n, int64_t k,
+                 const float* A, int64_t lda,
+                 const float* B, int64_t ldb,
+                 float* C, int64_t ldc,
+                 int N, int mode);
+
+/* Set the HIP stream (a hipStream_t passed as void*; NULL = null stream)
+ * used by every later call.  Returns 0. */
+int ozaki2_set_stream(void* stream);
+
+/* Bytes of workspace a call with these arguments needs (written to *bytes).
+ * Returns 0, or the argument error code as ozaki2_dgemm would. */
+int ozaki2_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode,
+                          size_t* bytes);
+
+/* Use caller-owned device memory (256-byte aligned) as workspace.  The
+ * library does not free it.  Pass (NULL, 0) to go back to library-owned
+ * workspace.  The memory must stay valid until replaced and must not be in
+ * use by another call in flight on another stream.  Returns 0, or -1 if ptr
+ * is not 256-byte aligned. */
+int ozaki2_set_workspace(void* ptr, size_t bytes);
+
+/* Synchronise the current stream, then report (in *status) and clear the
+ * device status bits (OZ2_STATUS_*) written by the most recent GEMM call on
+ * the current device.  Returns 0, -1 if status is NULL, or OZ2_ERR_HIP. */
+int ozaki2_get_device_status(int* status);
+
+/* Human-readable description of a return code.  Never NULL. */
+const char* ozaki2_status_string(int code);
+
+/* Library version and contract constants, e.g. "ozaki2 0.1 kc=64 ...". */
+const char* ozaki2_version(void);
+
+/* Free library-owned workspace and events.  Returns 0. */
+int ozaki2_finalize(void);
+
+/*
+ * ozaki2_query_constants -- host-only: the constants of Step 1 and of the
+ * scaling formulas for N moduli, as the library computes them.
+ *   moduli[N]       the moduli p_1..p_N (first N of the Section 3.1 list)
+ *   p_prime_prop    P'_prop = RD32(log2(P-1)/2 - 0.5) (Section 4; equals
+ *                   P'_accu of Section 2.3)
+ *   p_prime_fast    P'_fast = RD32(log2(P-1)/2 - 1.5) (Section 2.3)
+ *   delta           RU32(0.5 / (1 - 4 u32)), u32 = 2^-24 (Section 2.3)
+ *   log2_P          log2(P) as a binary64 approximation (informative)
+ * Any output pointer may be NULL.  Returns 0 or -1 if N is out of range.
+ */
+int ozaki2_query_constants(int N, int32_t* moduli, float* p_prime_prop,
+                           float* p_prime_fast, float* delta, double* log2_P);
+
+/*
+ * Stage timing.  ozaki2_set_timing(1) makes every later call record HIP
+ * events around its stages on the current stream; ozaki2_get_stage_times
+ * synchronises the stream and writes into ms[OZ2_NUM_STAGES] the summed
+ * milliseconds per stage since timing was enabled (or last read), and into
+ * *calls the number of calls timed, then resets the sums.
+ * Stages: 0 norms and exponents (K1), 1 convert and split (K2),
+ * 2 INT8 GEMMs (K3), 3 CRT and unscale (K4), 4 other (accurate-mode
+ * scale GEMM, zero fill).
+ */
+#define OZ2_NUM_STAGES 5
+int ozaki2_set_timing(int enable);
+int ozaki2_get_stage_times(double* ms, int* calls);
+
+/*
+ * ozaki2_debug_stages -- run Steps 1-3 of ozaki2_dgemm for binary64 A, B
+ * (same argument rules) and copy every intermediate to caller DEVICE
+ * buffers (any may be NULL to skip it):
+ *   eA[m], eB[n]      int32 log2(mu_i), log2(nu_j)
+ *   SA[m], SB[n]      binary64 rounded-up squared norms (0 in accurate mode)
+ *   RA[N*m*k]         int8 residues of A': element (t, i, h) at t*m*k + i*k + h
+ *   RB[N*n*k]         int8 residues of B': element (t, j, h) at t*n*k + j*k + h
+ *   Ct[m*n]           int32 product rmod(A',p_t) rmod(B',p_t) for modulus
+ *                     index t (0-based), column-major (i + j*m)
+ * Test hook for stage-by-stage comparison with a reference.  Synchronises
+ * the stream before returning.
+ */
+int ozaki2_debug_stages(int64_t m, int64_t n, int64_t k,
+                        const double* A, int64_t lda,
+                        const double* B, int64_t ldb,
+                        int N, int mode, int t,
+                        int32_t* eA, int32_t* eB, double* SA, double* SB,
+                        int8_t* RA, int8_t* RB, int32_t* Ct);
+
+/*
+ * ozaki2_debug_log2f -- y[i] = the binary32 log2 used by the scaling
+ * (correctly rounded to nearest), for n binary32 values x[i] in [1, 2];
+ * device pointers.  Test hook.  Synchronises the stream.
+ */
+int ozaki2_debug_log2f(const float* x, float* y, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OZAKI2_H */

@@ -1,0 +1,138 @@
+// oz2_k1_norm.hpp -- K1: rounded-up squared norms of the rows of A and the
+// columns of B, and the scale exponents log2(mu_i), log2(nu_j) of Step 2.
+//
+// Fixed summation order (the paper allows any order for the rounded-up sum;
+// a fixed one makes results reproducible): chunks of kKC consecutive entries,
+// each chunk summed left to right, then the chunk sums left to right; every
+// square and every addition rounded toward +inf in binary64.
+//
+// Pass 1 writes one partial sum per (chunk, vector); pass 2 folds the
+// partials in chunk order and evaluates Algorithm 1 or 2 per vector.
+#pragma once
+
+#include "oz2_math.hpp"
+#include "oz2_tables.hpp"
+
+namespace oz2 {
+
+constexpr int kKC = 64;
+constexpr int32_t kExpNonFinite = INT32_MIN;  // exponent sentinel: NaN output
+
+// Vectors stored with stride `ld` between consecutive entries (rows of a
+// column-major matrix): entry h of vector v is X[v + h * ld].  One lane per
+// vector (64 consecutive vectors per wave, so every load is a contiguous 512
+// bytes), one wave per chunk.
+template <typename T>
+__global__ __launch_bounds__(256) void k1_partials_strided(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
+    double* __restrict__ part, double* __restrict__ pmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t c = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (v >= nvec || c >= nchunks) return;
+  const int64_t h0 = c * kKC;
+  const int64_t len = k - h0 < kKC ? k - h0 : kKC;
+  const T* p = X + v + h0 * ld;
+  double s = 0.0, mx = 0.0;
+  if (len == kKC) {
+#pragma unroll
+    for (int b = 0; b < kKC; b += 16) {
+      double a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = (double)p[(int64_t)(b + i) * ld];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        s = ru_add(s, ru_square(a[i]));
+        mx = fmax(mx, fabs(a[i]));
+      }
+    }
+  } else {
+    for (int64_t h = 0; h < len; ++h) {
+      double a = (double)p[h * ld];
+      s = ru_add(s, ru_square(a));
+      mx = fmax(mx, fabs(a));
+    }
+  }
+  part[c * nvec + v] = s;
+  if (pmax) pmax[c * nvec + v] = mx;
+}
+
+// Vectors stored contiguously (columns of a column-major matrix): entry h of
+// vector v is X[h + v * ld].  One lane per (vector, chunk); lanes of a wave
+// take consecutive chunks.
+template <typename T>
+__global__ __launch_bounds__(256) void k1_partials_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
+    double* __restrict__ part, double* __restrict__ pmax) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= nvec * nchunks) return;
+  const int64_t v = g / nchunks;
+  const int64_t c = g - v * nchunks;
+  const int64_t h0 = c * kKC;
+  const int64_t len = k - h0 < kKC ? k - h0 : kKC;
+  const T* p = X + v * ld + h0;
+  double s = 0.0, mx = 0.0;
+  if (len == kKC) {
+#pragma unroll
+    for (int b = 0; b < kKC; b += 16) {
+      double a[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = (double)p[b + i];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        s = ru_add(s, ru_square(a[i]));
+        mx = fmax(mx, fabs(a[i]));
+      }
+    }
+  } else {
+    for (int64_t h = 0; h < len; ++h) {
+      double a = (double)p[h];
+      s = ru_add(s, ru_square(a));
+      mx = fmax(mx, fabs(a));
+    }
+  }
+  part[c * nvec + v] = s;
+  if (pmax) pmax[c * nvec + v] = mx;
+}
+
+// Pass 2: fold partial sums in chunk order and evaluate the exponent.
+// mode 0: Algorithm 2 (revised); mode 1: Algorithm 1 (original fast mode).
+// A squared norm that is NaN or +inf yields the sentinel exponent and sets
+// bit OZ2_STATUS_NONFINITE in *status.
+__global__ __launch_bounds__(256) void k1_fold(
+    const double* __restrict__ part, const double* __restrict__ pmax, int64_t nchunks,
+    int64_t nvec, int mode, const ModTable* __restrict__ tab, int32_t* __restrict__ e_out,
+    double* __restrict__ S_out, int* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvec) return;
+  double S = 0.0, mx = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    S = ru_add(S, part[c * nvec + v]);
+    if (pmax) mx = fmax(mx, pmax[c * nvec + v]);
+  }
+  if (S_out) S_out[v] = S;
+  int32_t e;
+  if (!(S <= 1.7976931348623157e308)) {
+    e = kExpNonFinite;
+    atomicOr(status, 1);
+  } else if (mode == 0) {
+    e = alg2_exponent(S, tab->p_prop);
+  } else {
+    e = alg1_exponent(S, mx, tab->p_fast, tab->delta);
+  }
+  e_out[v] = e;
+}
+
+// Status word reset at the start of each call (a kernel, not a memset, so
+// the call can be captured in a graph).
+__global__ void k_clear_status(int* status) {
+  if (threadIdx.x == 0) status[0] = 0;
+}
+
+// Exhaustive-check hook for the binary32 log2 of the scaling.
+__global__ void k_log2f(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = log2_rn32(x[i]);
+}
+
+}  // namespace oz2

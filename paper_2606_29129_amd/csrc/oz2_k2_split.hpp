@@ -1,0 +1,144 @@
+// oz2_k2_split.hpp -- K2: Step 2 and the residue part of Step 3.
+//
+// For every entry a of a row (column) with exponent e: a' = trunc(a 2^e)
+// (exact in binary64: a power-of-two scaling then a truncation), then the N
+// INT8 residues of a' -- rmod(a', p) in [-(p-1)/2, (p-1)/2] for odd p, and
+// the two's-complement low byte for p = 256 (congruent to rmod(a', 256); rmod
+// itself can give +128, which INT8 cannot hold).
+//
+// Residues: a' is split into signed 26-bit limbs, a' = sum_j x_j 2^(26 j)
+// (all limbs carry the sign of a', |x_j| < 2^26), so a' = y (mod p) with
+// y = sum_j x_j (2^(26 j) mod p), |y| < 2^36, exact in binary64.  Then
+// q = rint(y / p) is found from y * RN(1/p) (its error is below 2^-23, far
+// below the 1/(2p) distance of y/p from a half-integer), and r = y - q p is
+// exact: the symmetric residue, with no correction step.
+//
+// Output layout: plane t is a (Vp x Kp) int8 matrix, vector-major with the
+// k index contiguous (what the GEMM reads); padding rows and columns are 0.
+// Each lane converts 16 consecutive entries and stores 16 bytes per plane.
+#pragma once
+
+#include "oz2_k1_norm.hpp"
+#include "oz2_tables.hpp"
+
+namespace oz2 {
+
+template <int LIMBS>
+struct Limbs {
+  double x[LIMBS];
+};
+
+template <int LIMBS>
+OZ2_HD Limbs<LIMBS> make_limbs(double a, int32_t e) {
+  Limbs<LIMBS> L;
+  double v = (e == kExpNonFinite) ? 0.0 : trunc(ldexp(a, e));
+  if (!(v == v)) v = 0.0;  // NaN entries of a flagged row give 0
+#pragma unroll
+  for (int j = LIMBS - 1; j >= 1; --j) {
+    const double scale = ldexp(1.0, 26 * j);
+    double q = trunc(v * (1.0 / scale));
+    v = fma(-q, scale, v);
+    L.x[j] = q;
+  }
+  L.x[0] = v;
+  return L;
+}
+
+template <int LIMBS>
+OZ2_HD int residue_odd(const Limbs<LIMBS>& L, const double* pw, double p, double inv_p) {
+  double y = L.x[0];
+#pragma unroll
+  for (int j = 1; j < LIMBS; ++j) y = fma(L.x[j], pw[j], y);
+  double q = rint(y * inv_p);
+  return (int)fma(-q, p, y);
+}
+
+template <int LIMBS>
+OZ2_HD int residue_256(const Limbs<LIMBS>& L) {
+  return (int)(int8_t)(uint8_t)((int32_t)L.x[0] & 0xFF);
+}
+
+// Convert 16 entries of one vector and store their residues in all N planes.
+template <int LIMBS>
+__device__ __forceinline__ void split16_store(const double (&a)[16], int32_t e,
+                                              const ModTable* __restrict__ tab, int N,
+                                              int8_t* __restrict__ out, int64_t plane) {
+  Limbs<LIMBS> L[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) L[i] = make_limbs<LIMBS>(a[i], e);
+  // modulus 0 is 256
+  {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t b = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) b |= ((uint32_t)(uint8_t)residue_256<LIMBS>(L[4 * q + i])) << (8 * i);
+      w[q] = b;
+    }
+    *reinterpret_cast<uint4*>(out) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  for (int t = 1; t < N; ++t) {
+    const double p = tab->p[t];
+    const double ip = tab->inv_p[t];
+    const double* pw = tab->pow26[t];
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t b = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        b |= ((uint32_t)(uint8_t)(int8_t)residue_odd<LIMBS>(L[4 * q + i], pw, p, ip)) << (8 * i);
+      w[q] = b;
+    }
+    *reinterpret_cast<uint4*>(out + (int64_t)t * plane) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+// Strided vectors (rows of column-major A): entry h of vector v at
+// X[v + h ld].  Block: 64 vectors x 128 entries; lane = vector, each wave
+// converts two groups of 16 entries.
+template <typename T, int LIMBS>
+__global__ __launch_bounds__(256) void k2_split_strided(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
+    int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
+  if (v >= Vp) return;
+  const int32_t ev = v < nvec ? e[v] : 0;
+  const int64_t plane = Vp * Kp;
+#pragma unroll 1
+  for (int g = 0; g < 2; ++g) {
+    const int64_t h0 = (int64_t)blockIdx.y * 128 + wave * 32 + g * 16;
+    if (h0 >= Kp) break;
+    double a[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      a[i] = (v < nvec && h0 + i < k) ? (double)X[v + (h0 + i) * ld] : 0.0;
+    split16_store<LIMBS>(a, ev, tab, N, R + v * Kp + h0, plane);
+  }
+}
+
+// Contiguous vectors (columns of column-major B): entry h of vector v at
+// X[h + v ld].  One lane per (vector, group of 16 entries).
+template <typename T, int LIMBS>
+__global__ __launch_bounds__(256) void k2_split_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
+    int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  const int64_t groups = Kp / 16;
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= Vp * groups) return;
+  const int64_t v = g / groups;
+  const int64_t h0 = (g - v * groups) * 16;
+  const int32_t ev = v < nvec ? e[v] : 0;
+  double a[16];
+  const T* p = X + v * ld + h0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = (v < nvec && h0 + i < k) ? (double)p[i] : 0.0;
+  split16_store<LIMBS>(a, ev, tab, N, R + v * Kp + h0, Vp * Kp);
+}
+
+}  // namespace oz2

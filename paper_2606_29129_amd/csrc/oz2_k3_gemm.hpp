@@ -1,0 +1,204 @@
+// oz2_k3_gemm.hpp -- K3: the N INT8 matrix products of Step 3,
+//   C_t = rmod(A', p_t) rmod(B', p_t)   (INT8 x INT8 -> exact INT32),
+// on gfx950 MFMA (v_mfma_i32_32x32x32_i8), one modulus per grid row.
+//
+// Operands: plane t of RA is Mp x Kp and plane t of RB is Np x Kp, both with
+// the k index contiguous, so C_t = RA_t RB_t^T.  A workgroup of 256 lanes
+// (2 x 2 waves) computes a BM x BN tile; each wave owns (BM/2) x (BN/2) as
+// TM x TN blocks of 32 x 32.  Tiles of BK bytes of k are staged through LDS
+// (double-buffered; 16-byte chunks XOR-swizzled by row so that the 16-byte
+// fragment reads of a 32-row block hit distinct banks) and the next tile's
+// global loads are in flight while the current one feeds the MFMAs.
+//
+// Epilogue: |C_t| <= k * 128^2 fits INT32 for k <= 2^17 (Section 2.2).  The
+// product is reduced to U_t = C_t mod p_t in [0, p_t) and stored as one byte
+// per entry, in 32 x 32 blocks laid out in the MFMA accumulator order: block
+// (bi, bj) of plane t is 1024 contiguous bytes at ((t Nb + bj) Mb + bi) * 1024
+// (Mb = Mp/32, Nb = Np/32), lane l's 16 accumulators at byte 16 l.  K4 reads
+// the same order, so the stores and loads are 16 contiguous bytes per lane.
+// A debug variant stores the raw INT32 product of one modulus instead.
+#pragma once
+
+#include "oz2_tables.hpp"
+
+namespace oz2 {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Accumulator layout of a 32 x 32 INT32 MFMA block: register r of lane l
+// holds row acc_row(r, l), column acc_col(l).
+OZ2_HD int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+OZ2_HD int acc_col(int lane) { return lane & 31; }
+
+// 16-byte chunk swizzle inside an LDS row of BK bytes.
+template <int BK>
+__device__ __forceinline__ int swz_chunk(int row, int chunk) {
+  if constexpr (BK == 128) return chunk ^ ((row >> 1) & 7);
+  else return chunk ^ ((row >> 2) & 3);
+}
+
+// Map a workgroup id to (plane, tile).  Workgroups are dispatched
+// round-robin over the 8 XCDs of MI355X, each with its own L2; the id is
+// first remapped so that every XCD receives one contiguous range of the
+// (plane, tile) sequence, and inside a plane tiles are walked in groups of
+// GM tile rows, column by column, so that neighbouring workgroups share
+// operand panels in L2.
+__device__ __forceinline__ void tile_of(int id, int total, int tiles_m, int tiles_n,
+                                        int* plane, int* tm, int* tn) {
+  const int xcd = id & 7, slot = id >> 3;
+  const int per = total >> 3, extra = total & 7;
+  const int lin = (xcd < extra) ? xcd * (per + 1) + slot
+                                : extra * (per + 1) + (xcd - extra) * per + slot;
+  const int tiles = tiles_m * tiles_n;
+  *plane = lin / tiles;
+  const int in_plane = lin - *plane * tiles;
+  constexpr int GM = 8;
+  const int group = in_plane / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gm = tiles_m - first_m < GM ? tiles_m - first_m : GM;
+  const int in = in_plane - group * GM * tiles_n;
+  *tm = first_m + in % gm;
+  *tn = in / gm;
+}
+
+template <int BM, int BN, int BK, bool RAW>
+__global__ __launch_bounds__(256) void k3_gemm_i8(
+    const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
+    uint8_t* __restrict__ U, int32_t* __restrict__ Craw,
+    int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
+    const ModTable* __restrict__ tab, int t_raw) {
+  constexpr int TM = BM / 64, TN = BN / 64;      // 32x32 blocks per wave
+  constexpr int CH = BK / 16;                    // 16-byte chunks per row
+  constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
+  static_assert(A_LOADS * 256 == BM * CH && B_LOADS * 256 == BN * CH, "tile");
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][(BM + BN) * BK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tiles_m = (int)(Mp / BM), tiles_n = (int)(Np / BN);
+  int plane, tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &plane, &tm, &tn);
+  const int t = RAW ? t_raw : plane;
+
+  const int8_t* gA = RA + (int64_t)t * Mp * Kp + (int64_t)tm * BM * Kp;
+  const int8_t* gB = RB + (int64_t)t * Np * Kp + (int64_t)tn * BN * Kp;
+
+  v16i acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = v16i{0};
+
+  v4i ra[A_LOADS], rb[B_LOADS];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      int id = tid + 256 * i, row = id / CH, ch = id % CH;
+      ra[i] = *reinterpret_cast<const v4i*>(gA + (int64_t)row * Kp + k0 + ch * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      int id = tid + 256 * i, row = id / CH, ch = id % CH;
+      rb[i] = *reinterpret_cast<const v4i*>(gB + (int64_t)row * Kp + k0 + ch * 16);
+    }
+  };
+  auto lstore = [&](int buf) {
+    int8_t* sA = lds[buf];
+    int8_t* sB = lds[buf] + BM * BK;
+#pragma unroll
+    for (int i = 0; i < A_LOADS; ++i) {
+      int id = tid + 256 * i, row = id / CH, ch = id % CH;
+      *reinterpret_cast<v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_LOADS; ++i) {
+      int id = tid + 256 * i, row = id / CH, ch = id % CH;
+      *reinterpret_cast<v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16) = rb[i];
+    }
+  };
+
+  const int nk = (int)(Kp / BK);
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
+    const int8_t* sB = lds[buf] + BM * BK + (wn * (BN / 2)) * BK;
+#pragma unroll
+    for (int kk = 0; kk < BK / 32; ++kk) {
+      const int ch = kk * 2 + (lane >> 5);
+      v4i fa[TM], fb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        int row = i * 32 + (lane & 31);
+        fa[i] = *reinterpret_cast<const v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        int row = j * 32 + (lane & 31);
+        fb[j] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      lstore(buf ^ 1);
+    }
+    __syncthreads();
+  }
+
+  const int64_t Mb = Mp / 32;
+  if (RAW) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t col = (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+          if (row < m && col < n) Craw[row + col * m] = acc[i][j][r];
+        }
+      }
+    return;
+  }
+  const int64_t Nb = Np / 32;
+  const bool is256 = (t == 0);
+  const double p = tab->p[t], ip = tab->inv_p[t];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int c = acc[i][j][4 * q + e];
+          uint32_t u;
+          if (is256) {
+            u = (uint32_t)c & 0xFFu;
+          } else {
+            double y = (double)c;
+            double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
+            u = (uint32_t)(int)(r < 0.0 ? r + p : r);
+          }
+          b |= u << (8 * e);
+        }
+        w[q] = b;
+      }
+      const int64_t bi = (int64_t)tm * (BM / 32) + wm * (TM) + i;
+      const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;
+      uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+}  // namespace oz2

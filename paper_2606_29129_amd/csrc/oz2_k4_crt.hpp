@@ -1,0 +1,185 @@
+// oz2_k4_crt.hpp -- K4: CRT reconstruction (Step 3) and unscaling (Step 4).
+//
+// For each output entry, with U_t = C_t mod p_t from K3:
+//   X   = sum_t W_t U_t,   W_t = P_t q_t  (< P)           (eq. os2-C')
+//   C'' = X - P round(X / P)  in (-P/2, P/2)                (eq. os2-C'')
+//   C   = RN(C'' 2^-(e_i + f_j))                            (Step 4)
+// Because |A'B'| < P/2 (eq. os2-condition), C'' = A'B' exactly.
+//
+// Exact arithmetic in binary64: W_t is held as 39-bit slices w_ts, so each
+// slice sum Acc_s = sum_t w_ts U_t < 20 * 2^39 * 255 < 2^52 is exact.  The
+// quotient Q = round(X / P) (< 2^13) is estimated from a rounded X; every
+// R_s = Acc_s - Q P_s is exact, carries are propagated exactly, and an exact
+// signed comparison with P/2 corrects a quotient that is off by one.  The
+// magnitude is then rounded once, to nearest even, at the bit position that
+// the output format (binary64 or binary32, subnormals included) dictates.
+#pragma once
+
+#include "oz2_k1_norm.hpp"
+#include "oz2_k3_gemm.hpp"
+#include "oz2_tables.hpp"
+
+namespace oz2 {
+
+template <int S>
+OZ2_HD void normalize(double (&R)[S]) {
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) {
+    double c = floor(R[s] * 0x1p-39);
+    R[s] = fma(-c, 0x1p39, R[s]);
+    R[s + 1] += c;
+  }
+}
+
+// Sign of sum_s D_s 2^(39 s) after normalisation (lower slices in [0, 2^39)).
+template <int S>
+OZ2_HD int sign_of(double (&D)[S]) {
+  normalize(D);
+  if (D[S - 1] != 0.0) return D[S - 1] > 0.0 ? 1 : -1;
+#pragma unroll
+  for (int s = S - 2; s >= 0; --s)
+    if (D[s] != 0.0) return 1;
+  return 0;
+}
+
+// PREC = 53 (binary64) or 24 (binary32); EMIN_Q = exponent of the smallest
+// subnormal (-1074 or -149).
+template <int S, int PREC, int EMIN_Q>
+OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) {
+  // Quotient estimate.
+  double xf = acc[S - 1];
+#pragma unroll
+  for (int s = S - 2; s >= 0; --s) xf = fma(xf, 0x1p39, acc[s]);
+  const double Q = rint(xf * T.invP);
+  double R[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) R[s] = fma(-Q, T.P[s], acc[s]);
+  normalize(R);
+  // Bring R into (-P/2, P/2): R = C'' + jP with |j| <= 1 and |C''| < P/2.
+  {
+    double D[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) D[s] = R[s] - T.H[s];
+    if (sign_of(D) > 0) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) R[s] -= T.P[s];
+      normalize(R);
+    } else {
+#pragma unroll
+      for (int s = 0; s < S; ++s) D[s] = R[s] + T.H[s];
+      if (sign_of(D) < 0) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) R[s] += T.P[s];
+        normalize(R);
+      }
+    }
+  }
+  // Sign and magnitude (all slices in [0, 2^39) after normalisation).
+  const bool neg = R[S - 1] < 0.0;
+  if (neg) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) R[s] = -R[s];
+    normalize(R);
+  }
+  int j = S - 1;
+  while (j > 0 && R[j] == 0.0) --j;
+  if (R[j] == 0.0) return 0.0;
+  double frac;
+  const int L = 39 * j + split_pow2(R[j], &frac);   // floor(log2 |C''|)
+  const int q = (L - (PREC - 1)) > (E + EMIN_Q) ? (L - (PREC - 1)) : (E + EMIN_Q);
+  double res;
+  if (q <= 0) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = S - 1; s >= 0; --s) v += ldexp(R[s], 39 * s);  // exact: |C''| < 2^PREC
+    res = ldexp(v, -E);
+  } else if (q - 1 > L) {
+    res = 0.0;                                       // below half the quantum
+  } else {
+    const int sstar = (q - 1) / 39;                  // slice holding bit q-1
+    double Tq = 0.0, ftop = 0.0;
+    bool rest = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double vs = ldexp(R[s], 39 * s - q);           // exact
+      double I = floor(vs);
+      double f = vs - I;
+      Tq += I;
+      if (s == sstar) ftop = f;
+      else if (s < sstar && f != 0.0) rest = true;
+    }
+    const double cmp = ftop - 0.5;
+    const bool odd = fmod(Tq, 2.0) != 0.0;
+    const bool up = cmp > 0.0 || (cmp == 0.0 && (rest || odd));
+    res = ldexp(Tq + (up ? 1.0 : 0.0), q - E);
+  }
+  return neg ? -res : res;
+}
+
+// One wave per 32 x 32 block; lane l owns the 16 entries of the MFMA
+// accumulator layout (acc_row, acc_col).
+template <int S, typename TO>
+__global__ __launch_bounds__(256) void k4_crt(
+    const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
+    const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
+    int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t Mb = Mp / 32, Nb = Np / 32;
+  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t mb_used = (m + 31) / 32;
+  const int64_t nb_used = (n + 31) / 32;
+  if (blk >= mb_used * nb_used) return;
+  const int64_t bi = blk % mb_used, bj = blk / mb_used;
+  double acc[16][S];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
+  const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16;
+  const int64_t plane = Nb * Mb * 1024;
+  for (int t = 0; t < N; ++t) {
+    uint4 w = *reinterpret_cast<const uint4*>(src + (int64_t)t * plane);
+    uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+    double wt[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double u = (double)((ws[r >> 2] >> (8 * (r & 3))) & 0xFFu);
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
+    }
+  }
+  const int64_t col = bj * 32 + acc_col(lane);
+  if (col >= n) return;
+  const int32_t f = eB[col];
+  const ModTable& T = *tab;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t row = bi * 32 + acc_row(r, lane);
+    if (row >= m) continue;
+    const int32_t e = eA[row];
+    double v;
+    if (e == kExpNonFinite || f == kExpNonFinite) {
+      v = __builtin_nan("");
+    } else {
+      double a[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) a[s] = acc[r][s];
+      if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
+      else v = crt_unscale<S, 24, -149>(a, T, e + f);
+    }
+    C[row + col * ldc] = (TO)v;
+  }
+}
+
+// C = 0 (k = 0).
+template <typename TO>
+__global__ void k_zero(TO* __restrict__ C, int64_t m, int64_t n, int64_t ldc) {
+  int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= m * n) return;
+  int64_t j = g / m, i = g - j * m;
+  C[i + j * ldc] = (TO)0;
+}
+
+}  // namespace oz2

@@ -1,0 +1,138 @@
+// oz2_math.hpp -- scalar arithmetic of the scaling step (host and device).
+//
+// Everything here is exact or directed-rounded by construction, built from
+// round-to-nearest binary64 operations plus error-free transforms, so that
+// the GPU reproduces the rounded-up squared norms and the scale exponents of
+// Algorithms 1 and 2 bit for bit.  Compile with -ffp-contract=off: every
+// fused multiply-add is written explicitly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define OZ2_HD __host__ __device__ __forceinline__
+
+namespace oz2 {
+
+OZ2_HD double bits_to_f64(uint64_t u) { return __builtin_bit_cast(double, u); }
+OZ2_HD uint64_t f64_to_bits(double d) { return __builtin_bit_cast(uint64_t, d); }
+OZ2_HD float bits_to_f32(uint32_t u) { return __builtin_bit_cast(float, u); }
+OZ2_HD uint32_t f32_to_bits(float f) { return __builtin_bit_cast(uint32_t, f); }
+
+// Next binary64 above a finite non-negative x (0 -> smallest subnormal).
+OZ2_HD double next_up_nonneg(double x) { return bits_to_f64(f64_to_bits(x) + 1); }
+
+// Next binary32 above / below a finite f.
+OZ2_HD float next_up_f32(float f) {
+  if (f == 0.0f) return bits_to_f32(1u);
+  uint32_t b = f32_to_bits(f);
+  return bits_to_f32(f > 0.0f ? b + 1u : b - 1u);
+}
+OZ2_HD float next_down_f32(float f) { return -next_up_f32(-f); }
+
+// single_up(d) / single_down(d): binary64 -> binary32 rounded toward +inf /
+// -inf (Section 2.1 notation).  The cast rounds to nearest; one step fixes it.
+OZ2_HD float ru_f32(double d) {
+  float f = (float)d;
+  if ((double)f < d) f = next_up_f32(f);
+  return f;
+}
+OZ2_HD float rd_f32(double d) {
+  float f = (float)d;
+  if ((double)f > d) f = next_down_f32(f);
+  return f;
+}
+
+// RU(a*a) in binary64.  The FMA residual fma(a, a, -p) is exact when
+// a*a >= 2^-970; below that (|a| < 2^-480) the square is formed on a*2^600
+// and scaled back, rounding up once more (rounding up onto a coarser grid
+// after rounding up onto a finer one that contains it is one rounding up).
+OZ2_HD double ru_square(double a) {
+  double x = a < 0 ? -a : a;
+  if (x < 0x1p-480) {
+    if (x == 0.0) return 0.0;
+    double b = ldexp(x, 600);              // exact, b < 2^120
+    double pb = b * b;                     // >= 2^-948: residual exact
+    double eb = fma(b, b, -pb);
+    if (eb > 0.0) pb = next_up_nonneg(pb);
+    double r = ldexp(pb, -1200);           // one correctly rounded scaling
+    if (ldexp(r, 1200) < pb) r = next_up_nonneg(r);  // scaling back is exact
+    return r;
+  }
+  double p = x * x;
+  if (!(p <= 1.7976931348623157e308)) return p;  // inf (or NaN from a NaN)
+  double e = fma(x, x, -p);
+  return e > 0.0 ? next_up_nonneg(p) : p;
+}
+
+// RU(x + y) in binary64 for x, y >= 0 (Knuth's TwoSum gives the exact error).
+OZ2_HD double ru_add(double x, double y) {
+  double s = x + y;
+  if (!(s <= 1.7976931348623157e308)) return s;
+  double bb = s - x;
+  double err = (x - (s - bb)) + (y - bb);
+  return err > 0.0 ? next_up_nonneg(s) : s;
+}
+
+// floor(log2 x) of a finite x > 0 and the exact ratio x / 2^s in [1, 2).
+OZ2_HD int split_pow2(double x, double* frac) {
+  int e;
+  double f = frexp(x, &e);  // x = f 2^e, f in [0.5, 1)
+  *frac = 2.0 * f;
+  return e - 1;
+}
+
+// The binary32 log2 that stands in for the paper's fast log2: the binary64
+// log2 of a binary32 input rounded to nearest binary32.  For the inputs used
+// here (binary32 values in [1, 2]) this is the correctly rounded log2; the
+// test suite checks that for every such input.
+OZ2_HD float log2_rn32(float x) { return (float)log2((double)x); }
+
+// Algorithm 2 (Section 4): log2(mu_i) from the rounded-up squared norm S.
+//   s = floor(log2 S); t = RU32(0.5 log2f(S/2^s) + 2u32);
+//   w = RD32(P'_prop - 0.5 s); return floor(w - t).
+// S/2^s is converted to binary32 rounding up; S = 0 gives 0.
+OZ2_HD int alg2_exponent(double S, float p_prop) {
+  if (S == 0.0) return 0;
+  double x;
+  int s = split_pow2(S, &x);
+  float L = log2_rn32(ru_f32(x));
+  float t = ru_f32(0.5 * (double)L + 0x1p-23);        // exact sum, one rounding
+  float w = rd_f32((double)p_prop - 0.5 * (double)s);  // exact difference
+  return (int)floor((double)w - (double)t);            // exact difference
+}
+
+// Algorithm 1 (Section 2.3): the original fast-mode exponent.
+//   t = RU32(delta * RU32(log2f(S/2^s) + s));
+//   return floor(P'_fast - max(1, t)) - floor(log2 amax).
+OZ2_HD int alg1_exponent(double S, double amax, float p_fast, float delta) {
+  if (S == 0.0) return 0;
+  double x;
+  int s = split_pow2(S, &x);
+  float L = log2_rn32(ru_f32(x));
+  float u = ru_f32((double)L + (double)s);
+  float t = ru_f32((double)delta * (double)u);          // exact product
+  double mx = (double)t > 1.0 ? (double)t : 1.0;
+  int e1 = (int)floor((double)p_fast - mx);
+  double dummy;
+  return e1 - split_pow2(amax, &dummy);
+}
+
+// tilde-log2 of eq. (flog2) for an integer c > 0, rounded up (accurate mode):
+// RU32(log2f(c / 2^floor(log2 c)) + floor(log2 c)).
+OZ2_HD float tilde_log2_ru(int64_t c) {
+  double x;
+  int e = split_pow2((double)c, &x);
+  float L = log2_rn32(ru_f32(x));
+  return ru_f32((double)L + (double)e);
+}
+
+// Accurate mode (Section 2.3): log2 mu_i = log2 mu'_i
+//   + floor(P'_accu - RU32(delta * tilde-log2(max_h cbar_ih))).
+OZ2_HD int accurate_exponent(int e_first, int64_t cmax, float p_accu, float delta) {
+  if (cmax <= 0) return 0;
+  float corr = ru_f32((double)delta * (double)tilde_log2_ru(cmax));
+  return e_first + (int)floor((double)p_accu - (double)corr);
+}
+
+}  // namespace oz2

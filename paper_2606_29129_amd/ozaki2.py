@@ -1,0 +1,209 @@
+"""Python binding of libozaki2 (include/ozaki2.h): argument marshalling only.
+
+Every function named ``ozaki2_*`` calls the C entry point of the same name;
+pointer arguments accept a torch tensor (its ``data_ptr()``) or an int.  All
+computation happens in the HIP library; if it is not built or cannot be
+loaded, the first call raises.
+
+``dgemm``/``sgemm`` are conveniences for row-major torch tensors on the GPU:
+a row-major m x k tensor is the column-major k x m matrix, so C = A B is
+computed as the column-major C^T = B^T A^T by swapping the operands.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libozaki2.so")
+
+MODE_REVISED, MODE_ORIGINAL, MODE_ACCURATE = 0, 1, 2
+_MODES = {"revised": 0, "original": 1, "fast": 1, "accurate": 2}
+NUM_STAGES = 5
+STAGE_NAMES = ("norms_exponents", "convert_split", "int8_gemm", "crt_unscale", "other")
+
+_lib = None
+
+_c_i64, _c_int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+
+_SIGS = {
+    "ozaki2_dgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_sgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_set_stream": ([_vp], _c_int),
+    "ozaki2_workspace_size": ([_c_i64] * 3 + [_c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)], _c_int),
+    "ozaki2_set_workspace": ([_vp, ctypes.c_size_t], _c_int),
+    "ozaki2_get_device_status": ([ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_status_string": ([_c_int], ctypes.c_char_p),
+    "ozaki2_version": ([], ctypes.c_char_p),
+    "ozaki2_finalize": ([], _c_int),
+    "ozaki2_query_constants": ([_c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_double)], _c_int),
+    "ozaki2_set_timing": ([_c_int], _c_int),
+    "ozaki2_get_stage_times": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_debug_stages": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _c_int, _c_int, _c_int]
+                            + [_vp] * 7, _c_int),
+    "ozaki2_debug_log2f": ([_vp, _vp, _c_i64], _c_int),
+}
+
+
+class Ozaki2Error(RuntimeError):
+    def __init__(self, fn, code):
+        self.code = code
+        msg = lib().ozaki2_status_string(code).decode()
+        super().__init__(f"{fn} returned {code}: {msg}")
+
+
+def lib():
+    """The loaded libozaki2 (raises if the HIP library is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libozaki2.so is not built ({LIB_PATH}); run "
+                               "python -m paper_2606_29129_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check(fn, rc):
+    if rc != 0:
+        raise Ozaki2Error(fn, rc)
+    return rc
+
+
+# --- C entry points (same names) -------------------------------------------
+
+def ozaki2_dgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
+    return lib().ozaki2_dgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_sgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
+    return lib().ozaki2_sgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_set_stream(stream):
+    """stream: a torch.cuda.Stream, a raw hipStream_t as int, or None."""
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    return lib().ozaki2_set_stream(stream)
+
+
+def ozaki2_workspace_size(m, n, k, N, mode=MODE_REVISED):
+    b = ctypes.c_size_t(0)
+    _check("ozaki2_workspace_size", lib().ozaki2_workspace_size(m, n, k, N, mode, ctypes.byref(b)))
+    return b.value
+
+
+def ozaki2_set_workspace(ptr, nbytes):
+    return lib().ozaki2_set_workspace(_ptr(ptr), nbytes)
+
+
+def ozaki2_get_device_status():
+    s = ctypes.c_int(0)
+    _check("ozaki2_get_device_status", lib().ozaki2_get_device_status(ctypes.byref(s)))
+    return s.value
+
+
+def ozaki2_status_string(code):
+    return lib().ozaki2_status_string(code).decode()
+
+
+def ozaki2_version():
+    return lib().ozaki2_version().decode()
+
+
+def ozaki2_finalize():
+    return lib().ozaki2_finalize()
+
+
+def ozaki2_query_constants(N):
+    """dict(moduli, p_prime_prop, p_prime_fast, delta, log2_P) as the library
+    computes them (host only)."""
+    mod = (ctypes.c_int32 * 20)()
+    pp, pf, d = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    lp = ctypes.c_double()
+    _check("ozaki2_query_constants", lib().ozaki2_query_constants(
+        N, mod, ctypes.byref(pp), ctypes.byref(pf), ctypes.byref(d), ctypes.byref(lp)))
+    return dict(moduli=list(mod[:N]), p_prime_prop=pp.value, p_prime_fast=pf.value,
+                delta=d.value, log2_P=lp.value)
+
+
+def ozaki2_set_timing(enable):
+    return lib().ozaki2_set_timing(int(bool(enable)))
+
+
+def ozaki2_get_stage_times():
+    ms = (ctypes.c_double * NUM_STAGES)()
+    calls = ctypes.c_int(0)
+    _check("ozaki2_get_stage_times", lib().ozaki2_get_stage_times(ms, ctypes.byref(calls)))
+    return list(ms), calls.value
+
+
+def ozaki2_debug_stages(m, n, k, A, lda, B, ldb, N, mode, t,
+                        eA=None, eB=None, SA=None, SB=None, RA=None, RB=None, Ct=None):
+    return lib().ozaki2_debug_stages(m, n, k, _ptr(A), lda, _ptr(B), ldb, N, mode, t,
+                                     _ptr(eA), _ptr(eB), _ptr(SA), _ptr(SB), _ptr(RA),
+                                     _ptr(RB), _ptr(Ct))
+
+
+def ozaki2_debug_log2f(x, y, n):
+    return lib().ozaki2_debug_log2f(_ptr(x), _ptr(y), n)
+
+
+# --- torch conveniences ------------------------------------------------------
+
+def _mode(mode):
+    return _MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def _bind_current_stream(torch):
+    ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+
+
+def dgemm(A, B, N=14, mode="revised", out=None):
+    """C = A @ B for row-major float64 CUDA tensors A (m x k), B (k x n)."""
+    import torch
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("dgemm needs float64 tensors")
+    return _gemm(A, B, N, mode, out, ozaki2_dgemm)
+
+
+def sgemm(A, B, N=7, mode="revised", out=None):
+    """C = A @ B for row-major float32 CUDA tensors A (m x k), B (k x n)."""
+    import torch
+    if A.dtype != torch.float32 or B.dtype != torch.float32:
+        raise TypeError("sgemm needs float32 tensors")
+    return _gemm(A, B, N, mode, out, ozaki2_sgemm)
+
+
+def _gemm(A, B, N, mode, out, fn):
+    import torch
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[0]:
+        raise ValueError("shapes do not compose")
+    if not (A.is_cuda and B.is_cuda):
+        raise ValueError("tensors must be on the GPU")
+    A = A.contiguous()
+    B = B.contiguous()
+    m, k = A.shape
+    n = B.shape[1]
+    C = out if out is not None else torch.empty((m, n), dtype=A.dtype, device=A.device)
+    if not C.is_contiguous() or C.shape != (m, n):
+        raise ValueError("out must be a contiguous m x n tensor")
+    _bind_current_stream(torch)
+    # Column-major view: C^T (n x m, ld n) = B^T (n x k, ld n) * A^T (k x m, ld k).
+    rc = fn(n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), N, _mode(mode))
+    _check(fn.__name__, rc)
+    return C

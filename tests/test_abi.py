@@ -1,0 +1,84 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+the header declares, validates arguments before touching the device, and
+computes the same Step 1 constants as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import constants
+from paper_2606_29129_amd import ozaki2 as oz
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ozaki2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ozaki2_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(oz.LIB_PATH)
+    names = _declared()
+    assert "ozaki2_dgemm" in names and "ozaki2_sgemm" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding wraps each of them under the same name
+    for name in names:
+        assert callable(getattr(oz, name)), name
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 1, 1, 1, 1, 1, 1, 1, 14, 0), -1),
+    ((1, -1, 1, 1, 1, 1, 1, 1, 1, 14, 0), -2),
+    ((1, 1, -1, 1, 1, 1, 1, 1, 1, 14, 0), -3),
+    ((4, 4, 4, 0, 4, 1, 4, 1, 4, 14, 0), -4),
+    ((4, 4, 4, 1, 3, 1, 4, 1, 4, 14, 0), -5),
+    ((4, 4, 4, 1, 4, 0, 4, 1, 4, 14, 0), -6),
+    ((4, 4, 4, 1, 4, 1, 3, 1, 4, 14, 0), -7),
+    ((4, 4, 4, 1, 4, 1, 4, 0, 4, 14, 0), -8),
+    ((4, 4, 4, 1, 4, 1, 4, 1, 3, 14, 0), -9),
+    ((4, 4, 4, 1, 4, 1, 4, 1, 4, 1, 0), -10),
+    ((4, 4, 4, 1, 4, 1, 4, 1, 4, 21, 0), -10),
+    ((4, 4, 4, 1, 4, 1, 4, 1, 4, 14, 3), -11),
+    ((4, 4, 2**17 + 1, 1, 4, 1, 2**17 + 1, 1, 4, 14, 0), 1),
+])
+def test_argument_errors_are_reported_without_device_work(args, code):
+    assert oz.ozaki2_dgemm(*args) == code
+    assert oz.ozaki2_sgemm(*args) == code
+
+
+def test_quick_returns_need_no_device():
+    # m = 0 or n = 0: nothing to compute; only the operand with elements
+    # needs a (never dereferenced) pointer.
+    assert oz.ozaki2_dgemm(0, 5, 5, 0, 1, 8, 5, 0, 1, 14, 0) == 0
+    assert oz.ozaki2_dgemm(5, 0, 5, 8, 5, 0, 5, 0, 5, 14, 0) == 0
+
+
+def test_status_strings():
+    for c in (-3, 0, 1, 2, 3, 4, 5, 99):
+        assert isinstance(oz.ozaki2_status_string(c), str)
+    v = oz.ozaki2_version()
+    assert "kc=64" in v and "gfx950" in v
+
+
+@pytest.mark.parametrize("N", range(2, 21))
+def test_library_constants_match_oracle(N):
+    c = oz.ozaki2_query_constants(N)
+    assert c["moduli"] == list(constants.moduli(N))
+    assert np.float32(c["p_prime_prop"]) == np.float32(float(constants.p_prime_prop(N)))
+    assert np.float32(c["p_prime_fast"]) == np.float32(float(constants.p_prime_fast(N)))
+    assert np.float32(c["delta"]) == np.float32(float(constants.delta()))
+    _, P, _, _ = constants.step1(N)
+    assert abs(c["log2_P"] - np.log2(float(P))) < 1e-9
+
+
+def test_workspace_size_grows_with_problem():
+    a = oz.ozaki2_workspace_size(256, 256, 256, 14)
+    b = oz.ozaki2_workspace_size(1024, 1024, 1024, 14)
+    c = oz.ozaki2_workspace_size(1024, 1024, 1024, 20)
+    assert 0 < a < b < c
+    assert oz.ozaki2_workspace_size(0, 10, 10, 14) == 0

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path against the CPU oracle, stage by stage, through
+the C ABI.  Integer stages (exponents, residues, INT32 products) and the
+final C are compared bit for bit; the componentwise tolerance the product
+must meet, 2**-50 (|A||B|)_ij, is then implied with margin zero."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fp, ozaki2 as ref, scaling, constants
+from paper_2606_29129_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2606_29129_amd import ozaki2 as oz  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _colmajor(M, ld=None):
+    """Device buffer holding numpy matrix M (r x c) column-major with
+    leading dimension ld >= r."""
+    r, c = M.shape
+    ld = ld or max(1, r)
+    buf = np.zeros((c, ld), dtype=M.dtype)
+    buf[:, :r] = M.T
+    return torch.from_numpy(buf).to(DEV), ld
+
+
+def _gpu_dgemm(A, B, N, mode=0, lda=None, ldb=None, ldc=None):
+    m, k = A.shape
+    n = B.shape[1]
+    Ad, lda = _colmajor(A, lda)
+    Bd, ldb = _colmajor(B, ldb)
+    ldc = ldc or max(1, m)
+    Cd = torch.full((n, ldc), 7.0, dtype=torch.float64, device=DEV)
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    rc = oz.ozaki2_dgemm(m, n, k, Ad, lda, Bd, ldb, Cd, ldc, N, mode)
+    assert rc == 0, oz.ozaki2_status_string(rc)
+    torch.cuda.synchronize()
+    full = Cd.cpu().numpy()
+    if ldc > m:
+        assert (full[:, m:] == 7.0).all(), "padding rows of C were written"
+    return full[:, :m].T.copy()
+
+
+def _bits_equal(x, y):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return x.shape == y.shape and np.array_equal(x.view(np.uint64), y.view(np.uint64))
+
+
+def _gpu_stages(A, B, N, mode, t):
+    m, k = A.shape
+    n = B.shape[1]
+    Ad, lda = _colmajor(A)
+    Bd, ldb = _colmajor(B)
+    z = lambda cnt, dt: torch.zeros(max(cnt, 1), dtype=dt, device=DEV)
+    eA, eB = z(m, torch.int32), z(n, torch.int32)
+    SA, SB = z(m, torch.float64), z(n, torch.float64)
+    RA, RB = z(N * m * k, torch.int8), z(N * n * k, torch.int8)
+    Ct = z(m * n, torch.int32)
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    rc = oz.ozaki2_debug_stages(m, n, k, Ad, lda, Bd, ldb, N, mode, t,
+                                eA, eB, SA, SB, RA, RB, Ct)
+    assert rc == 0, oz.ozaki2_status_string(rc)
+    torch.cuda.synchronize()
+    return dict(eA=eA.cpu().numpy()[:m], eB=eB.cpu().numpy()[:n],
+                SA=SA.cpu().numpy()[:m], SB=SB.cpu().numpy()[:n],
+                RA=RA.cpu().numpy()[:N * m * k].reshape(N, m, k),
+                RB=RB.cpu().numpy()[:N * n * k].reshape(N, n, k),
+                Ct=Ct.cpu().numpy()[:m * n].reshape(n, m).T)
+
+
+def test_log2f_is_correctly_rounded_on_all_of_1_2():
+    """The binary32 log2 of the scaling, for every binary32 x in [1, 2], is
+    the correctly rounded log2 (checked against binary64 log2 away from
+    rounding midpoints, and against the oracle's decimal log2 near them)."""
+    bits = np.arange(0x3F800000, 0x40000001, dtype=np.uint32)
+    x = bits.view(np.float32)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty_like(xd)
+    assert oz.ozaki2_debug_log2f(xd, yd, x.size) == 0
+    y = yd.cpu().numpy()
+    y64 = np.log2(x.astype(np.float64))
+    f = y64.astype(np.float32)
+    # distance of y64 to the nearest binary32 rounding midpoint
+    up = np.nextafter(f, np.float32(np.inf)).astype(np.float64)
+    dn = np.nextafter(f, np.float32(-np.inf)).astype(np.float64)
+    f64 = f.astype(np.float64)
+    dist = np.minimum(np.abs(y64 - (f64 + up) / 2), np.abs(y64 - (f64 + dn) / 2))
+    near = dist < 2.0 ** -45
+    assert np.array_equal(y[~near], f[~near])
+    from fractions import Fraction
+    for i in np.nonzero(near)[0][:2000]:
+        assert float(y[i]) == float(fp.log2_rn32(Fraction(float(x[i]))))
+
+
+CASES = [
+    # (m, n, k, phi, N, seed)
+    (256, 256, 256, 0.5, 14, 0),     # the small configuration, exactly
+    (300, 280, 520, 1.0, 14, 1),     # several tiles in every dimension, ragged
+    (37, 301, 129, 2.0, 20, 2),      # N = 20: 78-bit integers, 4 CRT slices
+    (70, 33, 65, 4.0, 8, 3),         # heavy-tailed magnitudes, few moduli
+    (1, 1, 1, 1.0, 14, 4),
+    (5, 3, 2, 0.5, 2, 5),            # N = 2
+]
+
+
+@pytest.mark.parametrize("m,n,k,phi,N,seed", CASES)
+def test_stage_parity_and_result(m, n, k, phi, N, seed):
+    print(f"case m={m} n={n} k={k} phi={phi} N={N} seed={seed}", flush=True)
+    A, B = inputs.problem(m, n, k, phi, seed)
+    r = ref.gemm(A, B, N, ref.REVISED)
+    for t in sorted({0, 1, N - 1}):
+        g = _gpu_stages(A, B, N, 0, t)
+        assert _bits_equal(g["SA"], np.array(r["SA"])), "row norms"
+        assert _bits_equal(g["SB"], np.array(r["SB"])), "column norms"
+        assert list(g["eA"]) == r["e_rows"]
+        assert list(g["eB"]) == r["e_cols"]
+        for tt in range(N):
+            assert np.array_equal(g["RA"][tt], r["RA"][tt]), f"RA plane {tt}"
+            assert np.array_equal(g["RB"][tt], r["RB"][tt].T), f"RB plane {tt}"
+        assert np.array_equal(g["Ct"].astype(np.int64), r["G"][t]), f"INT32 product t={t}"
+    C = _gpu_dgemm(A, B, N)
+    assert _bits_equal(C, r["C"])
+    # determinism: a second run gives the same bits
+    assert _bits_equal(_gpu_dgemm(A, B, N), C)
+
+
+def test_leading_dimensions_and_padding_rows():
+    A, B = inputs.problem(45, 38, 70, 1.0, seed=7)
+    want = ref.dgemm(A, B, 14)
+    C = _gpu_dgemm(A, B, 14, lda=51, ldb=77, ldc=64)
+    assert _bits_equal(C, want)
+
+
+@pytest.mark.parametrize("s", [300, -300])
+def test_power_of_two_scaling_is_exact(s):
+    """Section 4: A -> 2**s A scales C by exactly 2**s, on the GPU."""
+    A, B = inputs.problem(96, 64, 160, 1.0, seed=8)
+    C0 = _gpu_dgemm(A, B, 14)
+    C1 = _gpu_dgemm(A * 2.0 ** s, B, 14)
+    assert _bits_equal(C1, C0 * 2.0 ** s)
+
+
+@pytest.mark.parametrize("c", [3.7e100, 3.7e-100, 2.0 ** 300])
+def test_extreme_scalings_match_oracle(c):
+    A, B = inputs.problem(40, 24, 96, 2.0, seed=9)
+    A = A * c
+    assert _bits_equal(_gpu_dgemm(A, B, 16), ref.dgemm(A, B, 16))
+
+
+def test_edge_values_match_oracle():
+    """Zero rows/columns, subnormal and huge entries, exact integers."""
+    rng = np.random.default_rng(10)
+    A, B = inputs.problem(33, 29, 70, 1.0, seed=10)
+    A[3, :] = 0.0
+    B[:, 5] = 0.0
+    A[7, :] = rng.integers(1, 2**52, 70) * 2.0 ** -1074        # subnormal row
+    A[9, :] *= 2.0 ** 500
+    B[:, 11] = np.arange(70) - 35.0
+    A[12, ::3] = 0.0
+    want = ref.dgemm(A, B, 14)
+    assert _bits_equal(_gpu_dgemm(A, B, 14), want)
+
+
+def test_all_ones_revised_exact():
+    """The Section 3.1 example with the proposed scaling: C = k alpha**2."""
+    for s in (-10, -2, 0, 7):
+        A, B = inputs.ones_problem(40, 40, 1024, s)
+        C = _gpu_dgemm(A, B, 20)
+        assert (C == 1024 * 4.0 ** s).all()
+
+
+def test_k_zero_writes_zero():
+    m, n = 17, 9
+    Cd = torch.full((n, m), 5.0, dtype=torch.float64, device=DEV)
+    Ad = torch.zeros(1, dtype=torch.float64, device=DEV)
+    assert oz.ozaki2_dgemm(m, n, 0, Ad, m, Ad, 1, Cd, m, 14, 0) == 0
+    torch.cuda.synchronize()
+    assert (Cd.cpu().numpy() == 0.0).all()
+
+
+def test_nonfinite_row_gives_nan_row_and_status():
+    A, B = inputs.problem(20, 10, 64, 1.0, seed=11)
+    A[4, 7] = np.nan
+    A[6, 2] = np.inf
+    C = _gpu_dgemm(A, B, 14)
+    assert oz.ozaki2_get_device_status() & 1
+    assert np.isnan(C[4]).all() and np.isnan(C[6]).all()
+    good = [i for i in range(20) if i not in (4, 6)]
+    want = ref.dgemm(A[good], B, 14)
+    assert _bits_equal(C[good], want)
+
+
+def test_torch_rowmajor_convenience():
+    A, B = inputs.problem(64, 48, 100, 0.5, seed=12)
+    Ad = torch.from_numpy(A).to(DEV)
+    Bd = torch.from_numpy(B).to(DEV)
+    C = oz.dgemm(Ad, Bd, N=14).cpu().numpy()
+    assert _bits_equal(C, ref.dgemm(A, B, 14))
+
+
+@pytest.mark.parametrize("N", [8, 12, 16, 20])
+def test_error_against_exact_product(N):
+    """The emulated product is within the a-priori truncation bound and, with
+    enough moduli, within 2**-50 (|A||B|)_ij of the exact product."""
+    from oracle import reference
+    A, B = inputs.problem(64, 64, 256, 1.0, seed=13)
+    C = _gpu_dgemm(A, B, N)
+    assert _bits_equal(C, ref.dgemm(A, B, N))
+    rows, cols = range(0, 64, 7), range(0, 64, 9)
+    e = reference.errors(C[np.ix_(rows, cols)], A, B, rows, cols)
+    if N >= 16:
+        assert e["max_comp"] < 2.0 ** -50
