@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Emulated DGEMM throughput (2mnk/t) of Ozaki scheme II, fast mode with the
+revised scale-invariant scaling, on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--size S] [--N N]
+                    [--phi PHI] [--mode revised|original]
+
+A step is one ozaki2_dgemm call (norms and exponents, convert and split, N
+INT8 GEMMs, CRT and unscale) on a fixed synthetic problem already resident in
+HBM.  Default workload: m = n = k = 16384, entries (rand - 0.5) exp(phi randn)
+with phi = 0.5 and seed 0 (the distribution of the paper's experiments), N =
+14 moduli.  Prints one JSON line with the throughput, the roofline position of
+the dominant kernel (the INT8 GEMM, timed with HIP events on the library's
+stream during the timed steps), the CPU oracle timed on a bounded sample of
+the same problem, and the native FP64 DGEMM of the same GPU for context.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, 5.0 POP/s
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k3_gemm_i8_traffic.txt")
+K3_SOURCE = os.path.join(ROOT, "paper_2606_29129_amd", "csrc", "oz2_k3_gemm.hpp")
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(m, n, k, N):
+    """HBM bytes per K3 launch from the committed rocprofv3 counter summary,
+    or None if it is missing, for another workload, or for older K3 code."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            key, val = line.split(":", 1)
+            kv[key.strip()] = val.strip()
+    try:
+        if kv.get("kernel_source_sha256") != _sha(K3_SOURCE):
+            return None
+        if kv.get("workload") != f"m={m} n={n} k={k} N={N}":
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0):
+    """Time the CPU oracle computing sampled entries of the same product from
+    scratch (row and column norms, exponents, residues, N dot products, CRT,
+    unscaling), and check the GPU's entries against it bit for bit."""
+    import numpy as np
+    from oracle import constants, ozaki2 as ref, reference, scaling
+
+    m, k = A_rm.shape
+    n = B_rm.shape[1]
+    rng = np.random.default_rng(seed)
+    pp = constants.p_prime_prop(N)
+    pf, d = constants.p_prime_fast(N), constants.delta()
+    done = exact_ok = 0
+    elapsed = 0.0
+    max_rel = 0.0
+    while elapsed < budget_s or done < 2:
+        i, j = int(rng.integers(m)), int(rng.integers(n))
+        row = A_rm[i].double().cpu().numpy()
+        col = B_rm[:, j].double().cpu().numpy()
+        t0 = time.perf_counter()
+        Si, Sj = scaling.norm_sq_ru(row), scaling.norm_sq_ru(col)
+        if mode == 0:
+            ei, fj = scaling.alg2_log2_mu(Si, pp), scaling.alg2_log2_mu(Sj, pp)
+        else:
+            ei = scaling.alg1_log2_mu(Si, float(np.max(np.abs(row))), pf, d)
+            fj = scaling.alg1_log2_mu(Sj, float(np.max(np.abs(col))), pf, d)
+        c, _, _ = ref.entry(row, col, ei, fj, N)
+        elapsed += time.perf_counter() - t0
+        g = float(C_cm[j, i])
+        exact_ok += int(np.float64(g).view(np.uint64) == np.float64(c).view(np.uint64))
+        R = reference.exact_dot(row, col)
+        if R != 0:
+            max_rel = max(max_rel, float(abs((type(R)(g) - R) / R)))
+        done += 1
+    return dict(value=2.0 * k * done / elapsed / 1e12, unit="TFLOPS", cores=1,
+                kind="oracle",
+                sample=f"{done} entries C_ij at seeded random (i, j), each computed from "
+                       f"its full row of A and column of B (k={k}), single Python thread",
+                seconds=round(elapsed, 2)), done, exact_ok, max_rel
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=16384, help="m = n = k")
+    ap.add_argument("--m", type=int)
+    ap.add_argument("--n", type=int)
+    ap.add_argument("--k", type=int)
+    ap.add_argument("--N", type=int, default=14)
+    ap.add_argument("--phi", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="revised", choices=["revised", "original"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-native", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the emulated DGEMM is a "
+              "single-GPU kernel pipeline); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_29129_amd import inputs
+    from paper_2606_29129_amd import ozaki2 as oz
+
+    m = args.m or args.size
+    n = args.n or args.size
+    k = args.k or args.size
+    N, mode = args.N, (0 if args.mode == "revised" else 1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    A_rm = inputs.ozaki_matrix_torch(m, k, args.phi, args.seed, 0, dev)
+    B_rm = inputs.ozaki_matrix_torch(k, n, args.phi, args.seed, 1, dev)
+    A_cm = A_rm.t().contiguous()          # column-major A, lda = m
+    B_cm = B_rm.t().contiguous()          # column-major B, ldb = k
+    C_cm = torch.empty((n, m), dtype=torch.float64, device=dev)   # ldc = m
+    ws_bytes = oz.ozaki2_workspace_size(m, n, k, N, mode)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    oz._check("ozaki2_set_workspace", oz.ozaki2_set_workspace(ws_ptr, ws_bytes))
+    stream = torch.cuda.current_stream()
+    oz.ozaki2_set_stream(stream.cuda_stream)
+    torch.cuda.synchronize()
+    _log(f"inputs {m}x{k} and {k}x{n} generated in {time.time() - t0:.1f}s; "
+         f"workspace {ws_bytes / 2**30:.2f} GiB")
+
+    def step():
+        rc = oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, N, mode)
+        if rc:
+            raise oz.Ozaki2Error("ozaki2_dgemm", rc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _log(f"warmup done ({args.warmup} steps)")
+
+    oz._check("ozaki2_set_timing", oz.ozaki2_set_timing(1))
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for s in range(args.steps):
+        step()
+        evs[s + 1].record(stream)
+    torch.cuda.synchronize()
+    stage_ms, calls = oz.ozaki2_get_stage_times()
+    oz.ozaki2_set_timing(0)
+    total_ms = evs[0].elapsed_time(evs[-1])
+    per_step = sorted(evs[s].elapsed_time(evs[s + 1]) for s in range(args.steps))
+    ms_per_step = total_ms / args.steps
+    ms_median = per_step[len(per_step) // 2]
+    flops = 2.0 * m * n * k
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    _log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step "
+         f"(median {ms_median:.3f}) -> {value:.1f} TFLOPS emulated")
+
+    st = {name: round(v / max(calls, 1), 4) for name, v in zip(oz.STAGE_NAMES, stage_ms)}
+    k3_ms = stage_ms[2] / max(calls, 1)
+    k3_ops = 2.0 * m * n * k * N
+    achieved = k3_ops / (k3_ms * 1e-3) / 1e12
+    traffic = load_traffic(m, n, k, N)
+    roofline = dict(kernel="k3_gemm_i8 (N INT8 GEMMs, one launch)", bound="mfma",
+                    achieved=round(achieved, 1), peak=INT8_PEAK_TOPS, unit="TOP/s",
+                    frac=round(achieved / INT8_PEAK_TOPS, 4), traffic=traffic,
+                    avg_launch_ms=round(k3_ms, 4), ops_per_launch=k3_ops)
+    _log(f"stages ms/call: {st}; K3 {achieved:.0f} TOP/s = "
+         f"{100 * achieved / INT8_PEAK_TOPS:.1f}% of INT8 peak")
+
+    native = None
+    if not args.no_native:
+        Cn = torch.matmul(A_rm, B_rm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        e0.record(stream)
+        for _ in range(reps):
+            torch.matmul(A_rm, B_rm, out=Cn)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        native = flops / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12
+        del Cn
+        _log(f"native FP64 torch.matmul: {native:.1f} TFLOPS")
+
+    cpu = None
+    sample_check = None
+    if not args.no_cpu_baseline:
+        cpu, done, ok, max_rel = cpu_baseline(A_rm, B_rm, C_cm, N, mode, args.cpu_seconds,
+                                              args.seed)
+        sample_check = dict(entries=done, bit_exact=ok, max_rel_err_vs_exact=max_rel)
+        _log(f"cpu oracle: {cpu['value']:.3e} TFLOPS on {done} entries; "
+             f"GPU entries bit-exact: {ok}/{done}; max rel err vs exact {max_rel:.3e}")
+
+    out = {
+        "metric": "Emulated DGEMM TFLOPS (2mnk/t) at fixed max rel. error; batched vs plain",
+        "value": round(value, 2),
+        "unit": "TFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "ms_median": round(ms_median, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "io_dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"square DGEMM m=n=k={m if m == n == k else (m, n, k)}, "
+                        f"entries (rand-0.5)*exp({args.phi}*randn) seed {args.seed}, "
+                        f"Ozaki-II {args.mode} fast-mode scaling, N={N} INT8 moduli, plain",
+            "m": m, "n": n, "k": k, "phi": args.phi, "N": N, "mode": args.mode,
+            "seed": args.seed, "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stage_ms_per_step": st,
+        "native_fp64_tflops": None if native is None else round(native, 2),
+        "sample_check": sample_check,
+        "context": {"paper_gh200_cublas_dgemm_tflops": 60.9,
+                    "paper_gh200_ozaki2_dgemm_tflops_up_to": 80.2},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,6 +8,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "ozaki2.h"
 #include "oz2_k1_norm.hpp"
 #include "oz2_k2_split.hpp"
@@ -30,7 +32,6 @@ struct DevState {
   ModTable* d_tables = nullptr;  // device address of g_tables
   void* ws = nullptr;            // library-owned workspace
   size_t ws_bytes = 0;
-  hipEvent_t ev[OZ2_NUM_STAGES + 1] = {};
 };
 
 DevState g_dev[kMaxDevices];
@@ -120,8 +121,6 @@ int ensure_device(int* dev_out) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_tables)) != hipSuccess) return OZ2_ERR_HIP;
     D.d_tables = reinterpret_cast<ModTable*>(p);
-    for (int i = 0; i <= OZ2_NUM_STAGES; ++i)
-      if (hipEventCreate(&D.ev[i]) != hipSuccess) return OZ2_ERR_HIP;
     D.ready = true;
   }
   *dev_out = dev;
@@ -152,21 +151,36 @@ int get_workspace(int dev, size_t bytes, char** out) {
   return 0;
 }
 
+// Stage timing: each timed call records OZ2_NUM_STAGES + 1 events on the
+// stream; nothing waits for them until ozaki2_get_stage_times.
+struct TimedCall {
+  hipEvent_t ev[OZ2_NUM_STAGES + 1];
+};
+std::vector<TimedCall> g_pending;
+std::vector<TimedCall> g_free;
+
 struct StageClock {
-  DevState* D;
   bool on;
-  StageClock(DevState* d) : D(d), on(g_timing != 0) {}
+  TimedCall tc;
+  StageClock() : on(g_timing != 0) {
+    if (!on) return;
+    if (!g_free.empty()) {
+      tc = g_free.back();
+      g_free.pop_back();
+    } else {
+      for (int i = 0; i <= OZ2_NUM_STAGES; ++i)
+        if (hipEventCreate(&tc.ev[i]) != hipSuccess) { on = false; return; }
+    }
+  }
   void mark(int i) {
-    if (on) (void)hipEventRecord(D->ev[i], g_stream);
+    if (on) (void)hipEventRecord(tc.ev[i], g_stream);
   }
   void finish() {
-    if (!on) return;
-    (void)hipEventSynchronize(D->ev[OZ2_NUM_STAGES]);
-    for (int s = 0; s < OZ2_NUM_STAGES; ++s) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, D->ev[s], D->ev[s + 1]) == hipSuccess) g_stage_ms[s] += ms;
-    }
-    ++g_timed_calls;
+    if (on) g_pending.push_back(tc);
+    on = false;
+  }
+  ~StageClock() {
+    if (on) g_free.push_back(tc);  // abandoned on an error path
   }
 };
 
@@ -223,7 +237,7 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   char* ws = nullptr;
   if ((rc = get_workspace(dev, L.total, &ws))) return rc;
 
-  StageClock clk(&D);
+  StageClock clk;
   clk.mark(0);
   // K1: squared norms and exponents.
   k_clear_status<<<1, 64, 0, g_stream>>>((int*)(ws + L.status));
@@ -371,14 +385,18 @@ const char* ozaki2_version(void) {
 }
 
 int ozaki2_finalize(void) {
+  (void)hipStreamSynchronize(g_stream);
+  for (auto& tc : g_pending) g_free.push_back(tc);
+  g_pending.clear();
+  for (auto& tc : g_free)
+    for (int i = 0; i <= OZ2_NUM_STAGES; ++i) (void)hipEventDestroy(tc.ev[i]);
+  g_free.clear();
   for (int d = 0; d < kMaxDevices; ++d) {
     DevState& D = g_dev[d];
     if (!D.ready) continue;
     if (hipSetDevice(d) != hipSuccess) continue;
     (void)hipDeviceSynchronize();
     if (D.ws) (void)hipFree(D.ws);
-    for (int i = 0; i <= OZ2_NUM_STAGES; ++i)
-      if (D.ev[i]) (void)hipEventDestroy(D.ev[i]);
     D = DevState();
   }
   return 0;
@@ -400,6 +418,9 @@ int ozaki2_query_constants(int N, int32_t* moduli, float* p_prime_prop, float* p
 }
 
 int ozaki2_set_timing(int enable) {
+  if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
+  for (auto& tc : g_pending) g_free.push_back(tc);
+  g_pending.clear();
   g_timing = enable;
   for (double& v : g_stage_ms) v = 0.0;
   g_timed_calls = 0;
@@ -408,6 +429,16 @@ int ozaki2_set_timing(int enable) {
 
 int ozaki2_get_stage_times(double* ms, int* calls) {
   if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
+  for (auto& tc : g_pending) {
+    if (hipEventSynchronize(tc.ev[OZ2_NUM_STAGES]) != hipSuccess) return OZ2_ERR_HIP;
+    for (int s = 0; s < OZ2_NUM_STAGES; ++s) {
+      float v = 0.f;
+      if (hipEventElapsedTime(&v, tc.ev[s], tc.ev[s + 1]) == hipSuccess) g_stage_ms[s] += v;
+    }
+    ++g_timed_calls;
+    g_free.push_back(tc);
+  }
+  g_pending.clear();
   for (int s = 0; s < OZ2_NUM_STAGES; ++s) {
     if (ms) ms[s] = g_stage_ms[s];
     g_stage_ms[s] = 0.0;

@@ -14,6 +14,13 @@ randn uses the Box-Muller transform on two further streams.  Matrix A uses
 streams 0, 1, 2 and matrix B streams 3, 4, 5 (rand, Box-Muller u1, u2); the
 entry (r, c) of an R x C matrix has index r * C + c.
 
+``ozaki_matrix_torch`` evaluates the same streams with torch integer ops on
+any device (integer arithmetic wraps modulo 2**64 exactly as in numpy, so the
+uniforms are bit-identical; the log/cos/exp of the Box-Muller and exp(phi z)
+steps use the device's math library and may differ from numpy's in the last
+bit).  Whichever generator produced a matrix, the oracle is given that same
+matrix.
+
 This module holds no part of the emulation method; both the HIP path and the
 CPU oracle consume the arrays it returns.
 """
@@ -78,3 +85,47 @@ def ones_problem(m: int, n: int, k: int, s: int):
     a = np.full((m, k), 2.0 ** s)
     b = np.full((k, n), 2.0 ** s)
     return a, b
+
+
+# --- the same streams with torch (any device) -------------------------------
+
+def _i64(u: int) -> int:
+    """An unsigned 64-bit constant as the int64 with the same bits."""
+    return u - (1 << 64) if u >= (1 << 63) else u
+
+
+def _t_shr(z, s: int):
+    """Logical right shift of int64 bit patterns."""
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def _t_mix64(z):
+    z = (z ^ _t_shr(z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _t_shr(z, 27)) * _i64(0x94D049BB133111EB)
+    return z ^ _t_shr(z, 31)
+
+
+def uniform_torch(seed: int, stream: int, start: int, count: int, device):
+    import torch
+    key = int(_key(seed, stream))
+    idx = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    x = _t_mix64(_i64(key) + idx * _i64(int(_GAMMA)))
+    return _t_shr(x, 11).to(torch.float64) * (2.0 ** -53)
+
+
+def ozaki_matrix_torch(rows: int, cols: int, phi: float, seed: int = 0, which: int = 0,
+                       device="cuda", chunk: int = 1 << 24):
+    """Same distribution and streams as ``ozaki_matrix``, as a row-major
+    float64 torch tensor on ``device``."""
+    import torch
+    total = rows * cols
+    out = torch.empty(total, dtype=torch.float64, device=device)
+    base = 3 * which
+    for s in range(0, total, chunk):
+        c = min(chunk, total - s)
+        r = uniform_torch(seed, base + 0, s, c, device)
+        u1 = uniform_torch(seed, base + 1, s, c, device)
+        u2 = uniform_torch(seed, base + 2, s, c, device)
+        z = torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos(2.0 * torch.pi * u2)
+        out[s:s + c] = (r - 0.5) * torch.exp(phi * z)
+    return out.view(rows, cols)
