@@ -19,6 +19,7 @@
 // A debug variant stores the raw INT32 product of one modulus instead.
 #pragma once
 
+#include "oz2_math.hpp"
 #include "oz2_tables.hpp"
 
 namespace oz2 {
@@ -118,39 +119,53 @@ __global__ __launch_bounds__(256) void k3_gemm_i8(
     }
   };
 
+  // Fragment reads for k-step kk of LDS buffer buf into register set F.
+  v4i fa[2][TM], fb[2][TN];
+  auto fload = [&](int buf, int kk, int F) {
+    const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
+    const int8_t* sB = lds[buf] + BM * BK + (wn * (BN / 2)) * BK;
+    const int ch = kk * 2 + (lane >> 5);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      int row = i * 32 + (lane & 31);
+      fa[F][i] = *reinterpret_cast<const v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      int row = j * 32 + (lane & 31);
+      fb[F][j] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
+    }
+  };
+  auto mfmas = [&](int F) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
+  };
+
+  // Pipeline: the global loads of tile kt+1 are in flight during all of
+  // tile kt; the LDS fragment reads of step kk+1 are in flight during the
+  // MFMAs of step kk (register double buffer); the next tile's first
+  // fragments are read right after the barrier that publishes it.
+  constexpr int KS = BK / 32;
   const int nk = (int)(Kp / BK);
   gload(0);
   lstore(0);
   __syncthreads();
+  if (nk > 1) gload(BK);
+  fload(0, 0, 0);
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
-    const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
-    const int8_t* sB = lds[buf] + BM * BK + (wn * (BN / 2)) * BK;
 #pragma unroll
-    for (int kk = 0; kk < BK / 32; ++kk) {
-      const int ch = kk * 2 + (lane >> 5);
-      v4i fa[TM], fb[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        int row = i * 32 + (lane & 31);
-        fa[i] = *reinterpret_cast<const v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16);
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        int row = j * 32 + (lane & 31);
-        fb[j] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
-      }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    for (int kk = 0; kk < KS; ++kk) {
+      if (kk + 1 < KS) fload(buf, kk + 1, (kk + 1) & 1);
+      mfmas(kk & 1);
     }
-    if (kt + 1 < nk) {
-      lstore(buf ^ 1);
-    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
+    if (kt + 2 < nk) gload((int64_t)(kt + 2) * BK);
+    if (kt + 1 < nk) fload(buf ^ 1, 0, 0);
   }
 
   const int64_t Mb = Mp / 32;

@@ -215,3 +215,55 @@ def test_error_against_exact_product(N):
     e = reference.errors(C[np.ix_(rows, cols)], A, B, rows, cols)
     if N >= 16:
         assert e["max_comp"] < 2.0 ** -50
+
+
+@pytest.mark.parametrize("m,n,k,phi,N,seed", [(300, 280, 520, 1.0, 14, 21), (37, 90, 129, 4.0, 20, 22)])
+def test_original_fast_mode_parity(m, n, k, phi, N, seed):
+    """Algorithm 1 (original fast mode): exponents, residues, products and C
+    equal the oracle bit for bit."""
+    A, B = inputs.problem(m, n, k, phi, seed)
+    r = ref.gemm(A, B, N, ref.ORIGINAL)
+    g = _gpu_stages(A, B, N, 1, N - 1)
+    assert list(g["eA"]) == r["e_rows"] and list(g["eB"]) == r["e_cols"]
+    assert np.array_equal(g["RA"][N - 1], r["RA"][N - 1])
+    assert np.array_equal(g["Ct"].astype(np.int64), r["G"][N - 1])
+    assert _bits_equal(_gpu_dgemm(A, B, N, mode=1), r["C"])
+
+
+def test_original_fast_mode_reproduces_crt_failure():
+    """Section 3.1: with Algorithm 1, N = 20, k = 1024 and all-ones inputs
+    scaled by alpha <= 2**-2, A'B' exceeds P/2 and the result is wrong; the
+    GPU reproduces the oracle's (wrong) result bit for bit, and the revised
+    mode gets the exact product."""
+    for s in (-4, -2, -1, 3):
+        A, B = inputs.ones_problem(32, 32, 1024, s)
+        want = ref.dgemm(A[:2], B[:, :2], 20, ref.ORIGINAL)
+        C = _gpu_dgemm(A, B, 20, mode=1)
+        assert _bits_equal(C[:2, :2], want)
+        exact = 1024 * 4.0 ** s
+        assert ((C == exact).all()) == (s > -2)
+        assert (_gpu_dgemm(A, B, 20, mode=0) == exact).all()
+
+
+def _gpu_sgemm(A, B, N, mode=0):
+    m, k = A.shape
+    n = B.shape[1]
+    Ad, lda = _colmajor(A.astype(np.float32))
+    Bd, ldb = _colmajor(B.astype(np.float32))
+    Cd = torch.empty((n, m), dtype=torch.float32, device=DEV)
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    rc = oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, N, mode)
+    assert rc == 0, oz.ozaki2_status_string(rc)
+    torch.cuda.synchronize()
+    return Cd.cpu().numpy().T.copy()
+
+
+@pytest.mark.parametrize("m,n,k,phi,N", [(130, 70, 300, 1.0, 7), (64, 64, 64, 1.5, 5), (33, 17, 257, 0.5, 9)])
+def test_sgemm_parity(m, n, k, phi, N):
+    """SGEMM emulation (Section 5): binary32 inputs, binary64 rounded-up
+    norms, C rounded once to binary32; equal to the oracle bit for bit."""
+    A, B = inputs.problem(m, n, k, phi, seed=N)
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    want = ref.sgemm(A32, B32, N)
+    got = _gpu_sgemm(A32, B32, N)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
