@@ -159,6 +159,44 @@ int ozaki2_set_timing(int enable);
 int ozaki2_get_stage_times(double* ms, int* calls);
 
 /*
+ * Batched emulated DGEMM.  One problem of a batch, column-major as for
+ * ozaki2_dgemm; N is its number of moduli (OZ2_N_MIN..OZ2_N_MAX).
+ */
+typedef struct oz2_problem {
+  int64_t m, n, k;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  int N;
+  int reserved; /* must be 0 */
+} oz2_problem;
+
+/*
+ * ozaki2_dgemm_batched -- C_i ~ A_i B_i for `batch` independent problems of
+ * any shapes and moduli counts (problems[] is a HOST array; the matrices are
+ * device memory), with mode OZ2_MODE_REVISED or OZ2_MODE_ORIGINAL.
+ *
+ * All problems are computed by one HIP graph launch: the stages of
+ * ozaki2_dgemm run once for the whole batch (one grid per stage) and the
+ * INT8 GEMMs of every problem and modulus run in one persistent kernel that
+ * takes tiles from a shared work list.  The graph is built on the first call
+ * with a given batch signature (shapes, N, mode, workspace) and replayed
+ * afterwards; only the matrix pointers are refreshed per call (a small host
+ * -> device copy inside the graph).  Results are bit-identical to calling
+ * ozaki2_dgemm on each problem.
+ *
+ * Returns 0; -1 if batch < 0; -2 if problems is NULL with batch > 0; -3 for
+ * an unsupported mode; or, for the first invalid problem, the code
+ * ozaki2_dgemm would return for it, with its index in *bad_index (may be
+ * NULL).  Nothing is launched on error.
+ */
+int ozaki2_dgemm_batched(int batch, const oz2_problem* problems, int mode,
+                         int* bad_index);
+
+/*
  * ozaki2_debug_stages -- run Steps 1-3 of ozaki2_dgemm for binary64 A, B
  * (same argument rules) and copy every intermediate to caller DEVICE
  * buffers (any may be NULL to skip it):

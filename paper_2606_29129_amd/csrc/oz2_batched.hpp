@@ -1,0 +1,126 @@
+// oz2_batched.hpp -- many independent emulated GEMMs of uneven shapes in a
+// handful of launches (captured once into a HIP graph by the host side).
+//
+// Every problem keeps its own workspace regions and constants table (its own
+// N).  The element-wise stages run as one 1-D grid per kernel: a block finds
+// its problem by binary search in a prefix sum of per-problem block counts
+// and runs the same body as the single-problem kernel.  The INT8 GEMM runs as
+// a persistent kernel: each workgroup repeatedly takes the next (problem,
+// plane, tile) item from a list sorted by decreasing cost, through one atomic
+// counter, until the list is exhausted.
+#pragma once
+
+#include "oz2_k1_norm.hpp"
+#include "oz2_k2_split.hpp"
+#include "oz2_k3_gemm.hpp"
+#include "oz2_k4_crt.hpp"
+
+namespace oz2 {
+
+constexpr int kBatchTile = 128;   // GEMM tile of the batched path (BM = BN)
+
+struct BatchProb {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t m, n, k, lda, ldb, ldc;
+  int64_t Mp, Np, Kp, nch;
+  int N, mode;
+  const ModTable* tab;
+  int32_t *eA, *eB;
+  double *partA, *partB, *maxA, *maxB, *SA, *SB;
+  int8_t *RA, *RB;
+  uint8_t* U;
+  int64_t k1a_gx;  // K1 strided grid width (height is ceil(nch/4))
+};
+
+// Stages with a per-problem block count.
+enum BatchStage { kB_K1A = 0, kB_K1B, kB_FOLDA, kB_FOLDB, kB_K2A, kB_K2B, kB_K4, kB_NSTAGES };
+
+// Problem owning global block `b`: largest p with prefix[p] <= b.
+__device__ __forceinline__ int find_problem(const int64_t* __restrict__ prefix, int batch,
+                                            int64_t b) {
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ probs,
+                                                const int64_t* __restrict__ prefix, int batch,
+                                                int stage, int* __restrict__ status) {
+  const int64_t* pre = prefix + (int64_t)stage * (batch + 1);
+  const int64_t b = blockIdx.x;
+  const int p = find_problem(pre, batch, b);
+  const int64_t local = b - pre[p];
+  const BatchProb& P = probs[p];
+  switch (stage) {
+    case kB_K1A: {
+      int64_t bx = local % P.k1a_gx, by = local / P.k1a_gx;
+      k1_partials_strided_body<double>(P.A, P.lda, P.m, P.k, P.nch, P.partA, P.maxA, bx, by);
+      break;
+    }
+    case kB_K1B:
+      k1_partials_contig_body<double>(P.B, P.ldb, P.n, P.k, P.nch, P.partB, P.maxB, local);
+      break;
+    case kB_FOLDA:
+      k1_fold_body(P.partA, P.maxA, P.nch, P.m, P.mode, P.tab, P.eA, P.SA, status, local);
+      break;
+    case kB_FOLDB:
+      k1_fold_body(P.partB, P.maxB, P.nch, P.n, P.mode, P.tab, P.eB, P.SB, status, local);
+      break;
+    case kB_K2A: {
+      const int64_t gx = (P.Mp + 255) / 256;
+      int64_t bx = local % gx, by = local / gx;
+      k2_split_strided_body<double, 4>(P.A, P.lda, P.m, P.k, P.eA, P.tab, P.N, P.RA, P.Mp,
+                                       P.Kp, bx, by);
+      break;
+    }
+    case kB_K2B:
+      k2_split_contig_body<double, 4>(P.B, P.ldb, P.n, P.k, P.eB, P.tab, P.N, P.RB, P.Np, P.Kp,
+                                      local);
+      break;
+    default:
+      k4_crt_body<4, double>(P.U, P.eA, P.eB, P.tab, P.N, P.m, P.n, P.Mp, P.Np, P.C, P.ldc,
+                             local);
+      break;
+  }
+}
+
+// Work item: problem (16 bits), plane (8 bits), tile row, tile column.
+struct WorkItem {
+  uint16_t p;
+  uint16_t t;
+  uint16_t tm;
+  uint16_t tn;
+};
+
+__global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ probs,
+                                               const WorkItem* __restrict__ items, int nitems,
+                                               int* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][2 * kBatchTile * 128];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= nitems) break;
+    const WorkItem w = items[i];
+    const BatchProb& P = probs[w.p];
+    gemm_tile<kBatchTile, kBatchTile, 128, 0>(P.RA, P.RB, P.U, nullptr, nullptr, P.m, P.n, P.Mp,
+                                             P.Np, P.Kp, P.tab, w.t, w.tm, w.tn, lds);
+  }
+}
+
+__global__ void kb_reset(int* __restrict__ counter, int* __restrict__ status) {
+  if (threadIdx.x == 0) {
+    counter[0] = 0;
+    status[0] = 0;
+  }
+}
+
+}  // namespace oz2

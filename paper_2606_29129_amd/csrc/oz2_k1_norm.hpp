@@ -23,12 +23,12 @@ constexpr int32_t kExpNonFinite = INT32_MIN;  // exponent sentinel: NaN output
 // vector (64 consecutive vectors per wave, so every load is a contiguous 512
 // bytes), one wave per chunk.
 template <typename T>
-__global__ __launch_bounds__(256) void k1_partials_strided(
+__device__ __forceinline__ void k1_partials_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax) {
+    double* __restrict__ part, double* __restrict__ pmax, int64_t bx, int64_t by) {
   const int lane = threadIdx.x & 63;
-  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t c = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int64_t v = bx * 64 + lane;
+  const int64_t c = by * 4 + (threadIdx.x >> 6);
   if (v >= nvec || c >= nchunks) return;
   const int64_t h0 = c * kKC;
   const int64_t len = k - h0 < kKC ? k - h0 : kKC;
@@ -57,14 +57,21 @@ __global__ __launch_bounds__(256) void k1_partials_strided(
   if (pmax) pmax[c * nvec + v] = mx;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k1_partials_strided(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
+    double* __restrict__ part, double* __restrict__ pmax) {
+  k1_partials_strided_body<T>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x, blockIdx.y);
+}
+
 // Vectors stored contiguously (columns of a column-major matrix): entry h of
 // vector v is X[h + v * ld].  One lane per (vector, chunk); lanes of a wave
 // take consecutive chunks.
 template <typename T>
-__global__ __launch_bounds__(256) void k1_partials_contig(
+__device__ __forceinline__ void k1_partials_contig_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double* __restrict__ part, double* __restrict__ pmax, int64_t bx) {
+  const int64_t g = bx * 256 + threadIdx.x;
   if (g >= nvec * nchunks) return;
   const int64_t v = g / nchunks;
   const int64_t c = g - v * nchunks;
@@ -95,15 +102,22 @@ __global__ __launch_bounds__(256) void k1_partials_contig(
   if (pmax) pmax[c * nvec + v] = mx;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k1_partials_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
+    double* __restrict__ part, double* __restrict__ pmax) {
+  k1_partials_contig_body<T>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x);
+}
+
 // Pass 2: fold partial sums in chunk order and evaluate the exponent.
 // mode 0: Algorithm 2 (revised); mode 1: Algorithm 1 (original fast mode).
 // A squared norm that is NaN or +inf yields the sentinel exponent and sets
 // bit OZ2_STATUS_NONFINITE in *status.
-__global__ __launch_bounds__(256) void k1_fold(
+__device__ __forceinline__ void k1_fold_body(
     const double* __restrict__ part, const double* __restrict__ pmax, int64_t nchunks,
     int64_t nvec, int mode, const ModTable* __restrict__ tab, int32_t* __restrict__ e_out,
-    double* __restrict__ S_out, int* __restrict__ status) {
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double* __restrict__ S_out, int* __restrict__ status, int64_t bx) {
+  const int64_t v = bx * 256 + threadIdx.x;
   if (v >= nvec) return;
   double S = 0.0, mx = 0.0;
   for (int64_t c = 0; c < nchunks; ++c) {
@@ -121,6 +135,61 @@ __global__ __launch_bounds__(256) void k1_fold(
     e = alg1_exponent(S, mx, tab->p_fast, tab->delta);
   }
   e_out[v] = e;
+}
+
+__global__ __launch_bounds__(256) void k1_fold(
+    const double* __restrict__ part, const double* __restrict__ pmax, int64_t nchunks,
+    int64_t nvec, int mode, const ModTable* __restrict__ tab, int32_t* __restrict__ e_out,
+    double* __restrict__ S_out, int* __restrict__ status) {
+  k1_fold_body(part, pmax, nchunks, nvec, mode, tab, e_out, S_out, status, blockIdx.x);
+}
+
+// Accurate mode, first scale (Section 2.3): e'_v = 5 - floor(log2 max|a|) from
+// the folded chunk maxima.  A zero vector gets kExpZero (its bar row is 0);
+// a non-finite one gets kExpNonFinite and sets the status bit.
+constexpr int32_t kExpZero = INT32_MIN + 1;
+
+__global__ __launch_bounds__(256) void k1_fold_first(
+    const double* __restrict__ part, const double* __restrict__ pmax, int64_t nchunks,
+    int64_t nvec, int32_t* __restrict__ e1_out, int* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvec) return;
+  double S = 0.0, mx = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    S = ru_add(S, part[c * nvec + v]);
+    mx = fmax(mx, pmax[c * nvec + v]);
+  }
+  int32_t e;
+  if (!(S <= 1.7976931348623157e308)) {
+    e = kExpNonFinite;
+    atomicOr(status, 1);
+  } else if (mx == 0.0) {
+    e = kExpZero;
+  } else {
+    double f;
+    e = 5 - split_pow2(mx, &f);
+  }
+  e1_out[v] = e;
+}
+
+// Accurate mode, final exponent: log2 mu = e' + floor(P'_accu - RU32(delta *
+// tilde-log2(max_h cbar))) (the accurate-mode formula of Section 2.3).
+__global__ __launch_bounds__(256) void k1_accurate_exponent(
+    const int32_t* __restrict__ e1, const int32_t* __restrict__ cmax, int64_t nvec,
+    const ModTable* __restrict__ tab, int32_t* __restrict__ e_out) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvec) return;
+  const int32_t a = e1[v];
+  int32_t e;
+  if (a == kExpNonFinite) e = kExpNonFinite;
+  else if (a == kExpZero) e = 0;
+  else e = accurate_exponent(a, (int64_t)cmax[v], tab->p_prop, tab->delta);
+  e_out[v] = e;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // Status word reset at the start of each call (a kernel, not a memset, so

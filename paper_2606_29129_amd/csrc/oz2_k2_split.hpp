@@ -96,23 +96,23 @@ __device__ __forceinline__ void split16_store(const double (&a)[16], int32_t e,
 }
 
 // Strided vectors (rows of column-major A): entry h of vector v at
-// X[v + h ld].  Block: 64 vectors x 128 entries; lane = vector, each wave
-// converts two groups of 16 entries.
+// X[v + h ld].  A block of 256 lanes covers 256 vectors x 128 entries; lane =
+// vector, so every load instruction reads 64 consecutive entries of one
+// column (512 contiguous bytes), and each lane converts its 128 entries in
+// 8 groups of 16, writing one whole 128-byte line per plane.
 template <typename T, int LIMBS>
-__global__ __launch_bounds__(256) void k2_split_strided(
+__device__ __forceinline__ void k2_split_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
-    int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t v = (int64_t)blockIdx.x * 64 + lane;
+    int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx, int64_t by) {
+  const int64_t v = bx * 256 + threadIdx.x;
   if (v >= Vp) return;
   const int32_t ev = v < nvec ? e[v] : 0;
   const int64_t plane = Vp * Kp;
+  const int64_t hb = by * 128;
 #pragma unroll 1
-  for (int g = 0; g < 2; ++g) {
-    const int64_t h0 = (int64_t)blockIdx.y * 128 + wave * 32 + g * 16;
-    if (h0 >= Kp) break;
+  for (int g = 0; g < 8; ++g) {
+    const int64_t h0 = hb + g * 16;
     double a[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
@@ -121,15 +121,23 @@ __global__ __launch_bounds__(256) void k2_split_strided(
   }
 }
 
-// Contiguous vectors (columns of column-major B): entry h of vector v at
-// X[h + v ld].  One lane per (vector, group of 16 entries).
 template <typename T, int LIMBS>
-__global__ __launch_bounds__(256) void k2_split_contig(
+__global__ __launch_bounds__(256) void k2_split_strided(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
     int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  k2_split_strided_body<T, LIMBS>(X, ld, nvec, k, e, tab, N, R, Vp, Kp, blockIdx.x, blockIdx.y);
+}
+
+// Contiguous vectors (columns of column-major B): entry h of vector v at
+// X[h + v ld].  One lane per (vector, group of 16 entries).
+template <typename T, int LIMBS>
+__device__ __forceinline__ void k2_split_contig_body(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
+    int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx) {
   const int64_t groups = Kp / 16;
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t g = bx * 256 + threadIdx.x;
   if (g >= Vp * groups) return;
   const int64_t v = g / groups;
   const int64_t h0 = (g - v * groups) * 16;
@@ -139,6 +147,75 @@ __global__ __launch_bounds__(256) void k2_split_contig(
 #pragma unroll
   for (int i = 0; i < 16; ++i) a[i] = (v < nvec && h0 + i < k) ? (double)p[i] : 0.0;
   split16_store<LIMBS>(a, ev, tab, N, R + v * Kp + h0, Vp * Kp);
+}
+
+template <typename T, int LIMBS>
+__global__ __launch_bounds__(256) void k2_split_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
+    int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  k2_split_contig_body<T, LIMBS>(X, ld, nvec, k, e, tab, N, R, Vp, Kp, blockIdx.x);
+}
+
+// Accurate mode: abar = ceil(|a| 2^e') in [0, 64] (Section 2.3), one int8
+// plane in the GEMM layout.  Vectors with exponent kExpZero or
+// kExpNonFinite give zeros.
+OZ2_HD int8_t bar_value(double a, int32_t e) {
+  if (e == kExpZero || e == kExpNonFinite) return 0;
+  double v = ceil(ldexp(fabs(a), e));
+  return (int8_t)(v == v ? v : 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k2_bar_strided(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= Vp) return;
+  const int32_t ev = v < nvec ? e[v] : kExpZero;
+  const int64_t hb = (int64_t)blockIdx.y * 128;
+#pragma unroll 1
+  for (int g = 0; g < 8; ++g) {
+    const int64_t h0 = hb + g * 16;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t b = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t h = h0 + 4 * q + i;
+        double a = (v < nvec && h < k) ? (double)X[v + h * ld] : 0.0;
+        b |= (uint32_t)(uint8_t)bar_value(a, ev) << (8 * i);
+      }
+      w[q] = b;
+    }
+    *reinterpret_cast<uint4*>(R + v * Kp + h0) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k2_bar_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  const int64_t groups = Kp / 16;
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= Vp * groups) return;
+  const int64_t v = g / groups;
+  const int64_t h0 = (g - v * groups) * 16;
+  const int32_t ev = v < nvec ? e[v] : kExpZero;
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t h = h0 + 4 * q + i;
+      double a = (v < nvec && h < k) ? (double)X[v * ld + h] : 0.0;
+      b |= (uint32_t)(uint8_t)bar_value(a, ev) << (8 * i);
+    }
+    w[q] = b;
+  }
+  *reinterpret_cast<uint4*>(R + v * Kp + h0) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 }  // namespace oz2

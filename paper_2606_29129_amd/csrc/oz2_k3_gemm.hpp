@@ -16,7 +16,10 @@
 // (bi, bj) of plane t is 1024 contiguous bytes at ((t Nb + bj) Mb + bi) * 1024
 // (Mb = Mp/32, Nb = Np/32), lane l's 16 accumulators at byte 16 l.  K4 reads
 // the same order, so the stores and loads are 16 contiguous bytes per lane.
-// A debug variant stores the raw INT32 product of one modulus instead.
+// Other epilogues (EPI): 1 stores the raw INT32 product of one plane (test
+// hook); 2 (accurate mode's scale GEMM on the bar planes, Section 2.3) does
+// not store the product at all: it folds it into row and column maxima with
+// integer atomicMax (entries are >= 0, and the maxima start at 0).
 #pragma once
 
 #include "oz2_math.hpp"
@@ -63,24 +66,21 @@ __device__ __forceinline__ void tile_of(int id, int total, int tiles_m, int tile
   *tn = in / gm;
 }
 
-template <int BM, int BN, int BK, bool RAW>
-__global__ __launch_bounds__(256) void k3_gemm_i8(
+// One BM x BN output tile of plane t (tile row tm, tile column tn).
+template <int BM, int BN, int BK, int EPI>
+__device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
-    uint8_t* __restrict__ U, int32_t* __restrict__ Craw,
+    uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
-    const ModTable* __restrict__ tab, int t_raw) {
+    const ModTable* __restrict__ tab, int t, int tm, int tn,
+    int8_t (*__restrict__ lds)[(BM + BN) * BK]) {
   constexpr int TM = BM / 64, TN = BN / 64;      // 32x32 blocks per wave
   constexpr int CH = BK / 16;                    // 16-byte chunks per row
   constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
   static_assert(A_LOADS * 256 == BM * CH && B_LOADS * 256 == BN * CH, "tile");
-  __shared__ __attribute__((aligned(16))) int8_t lds[2][(BM + BN) * BK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int tiles_m = (int)(Mp / BM), tiles_n = (int)(Np / BN);
-  int plane, tm, tn;
-  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &plane, &tm, &tn);
-  const int t = RAW ? t_raw : plane;
 
   const int8_t* gA = RA + (int64_t)t * Mp * Kp + (int64_t)tm * BM * Kp;
   const int8_t* gB = RB + (int64_t)t * Np * Kp + (int64_t)tn * BN * Kp;
@@ -169,7 +169,8 @@ __global__ __launch_bounds__(256) void k3_gemm_i8(
   }
 
   const int64_t Mb = Mp / 32;
-  if (RAW) {
+  if constexpr (EPI == 1) {
+    int32_t* Craw = aux0;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -181,6 +182,37 @@ __global__ __launch_bounds__(256) void k3_gemm_i8(
           if (row < m && col < n) Craw[row + col * m] = acc[i][j][r];
         }
       }
+    return;
+  }
+  if constexpr (EPI == 2) {
+    int32_t* rmax = aux0;   // per row of the product (Mp entries)
+    int32_t* cmax = aux1;   // per column (Np entries)
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int v = acc[i][0][r];
+#pragma unroll
+        for (int j = 1; j < TN; ++j) v = v > acc[i][j][r] ? v : acc[i][j][r];
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+          int u = __shfl_xor(v, o);
+          v = v > u ? v : u;
+        }
+        if ((lane & 31) == 0)
+          atomicMax(rmax + (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane), v);
+      }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      int v = acc[0][j][0];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v = v > acc[i][j][r] ? v : acc[i][j][r];
+      int u = __shfl_xor(v, 32);
+      v = v > u ? v : u;
+      if (lane < 32) atomicMax(cmax + (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane), v);
+    }
     return;
   }
   const int64_t Nb = Np / 32;
@@ -214,6 +246,20 @@ __global__ __launch_bounds__(256) void k3_gemm_i8(
       uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
       *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
     }
+}
+
+template <int BM, int BN, int BK, int EPI>
+__global__ __launch_bounds__(256) void k3_gemm_i8(
+    const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
+    uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
+    int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
+    const ModTable* __restrict__ tab, int t_raw) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][(BM + BN) * BK];
+  const int tiles_m = (int)(Mp / BM), tiles_n = (int)(Np / BN);
+  int plane, tm, tn;
+  tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &plane, &tm, &tn);
+  const int t = EPI != 0 ? t_raw : plane;
+  gemm_tile<BM, BN, BK, EPI>(RA, RB, U, aux0, aux1, m, n, Mp, Np, Kp, tab, t, tm, tn, lds);
 }
 
 }  // namespace oz2

@@ -119,13 +119,13 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
 // One wave per 32 x 32 block; lane l owns the 16 entries of the MFMA
 // accumulator layout (acc_row, acc_col).
 template <int S, typename TO>
-__global__ __launch_bounds__(256) void k4_crt(
+__device__ __forceinline__ void k4_crt_body(
     const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
     const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
-    int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc) {
+    int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc, int64_t bx) {
   const int lane = threadIdx.x & 63;
   const int64_t Mb = Mp / 32, Nb = Np / 32;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t blk = bx * 4 + (threadIdx.x >> 6);
   const int64_t mb_used = (m + 31) / 32;
   const int64_t nb_used = (n + 31) / 32;
   if (blk >= mb_used * nb_used) return;
@@ -171,6 +171,14 @@ __global__ __launch_bounds__(256) void k4_crt(
     }
     C[row + col * ldc] = (TO)v;
   }
+}
+
+template <int S, typename TO>
+__global__ __launch_bounds__(256) void k4_crt(
+    const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
+    const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
+    int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc) {
+  k4_crt_body<S, TO>(U, eA, eB, tab, N, m, n, Mp, Np, C, ldc, blockIdx.x);
 }
 
 // C = 0 (k = 0).

@@ -16,6 +16,9 @@
 #include "oz2_k3_gemm.hpp"
 #include "oz2_k4_crt.hpp"
 #include "oz2_tables.hpp"
+#include "oz2_batched.hpp"
+
+#include <algorithm>
 
 using namespace oz2;
 
@@ -59,12 +62,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   int64_t Mp, Np, Kp, nch;
   size_t eA, eB, SA, SB, partA, partB, maxA, maxB, RA, RB, U, status, total;
+  size_t e1A, e1B, cmaxA, cmaxB, barA, barB;  // accurate mode only
 };
 
-Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode) {
+Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t tile = kBM) {
   Layout L;
-  L.Mp = round_up(m > 0 ? m : 1, kBM);
-  L.Np = round_up(n > 0 ? n : 1, kBN);
+  L.Mp = round_up(m > 0 ? m : 1, tile);
+  L.Np = round_up(n > 0 ? n : 1, tile);
   L.Kp = round_up(k > 0 ? k : 1, kBK);
   L.nch = (k + kKC - 1) / kKC;
   size_t off = 0;
@@ -76,9 +80,16 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode) {
   L.SB = take(8 * (size_t)n);
   L.partA = take(8 * (size_t)L.nch * m);
   L.partB = take(8 * (size_t)L.nch * n);
-  const bool need_max = (mode == OZ2_MODE_ORIGINAL);
+  const bool need_max = (mode != OZ2_MODE_REVISED);
   L.maxA = need_max ? take(8 * (size_t)L.nch * m) : 0;
   L.maxB = need_max ? take(8 * (size_t)L.nch * n) : 0;
+  const bool acc = (mode == OZ2_MODE_ACCURATE);
+  L.e1A = acc ? take(4 * (size_t)L.Mp) : 0;
+  L.e1B = acc ? take(4 * (size_t)L.Np) : 0;
+  L.cmaxA = acc ? take(4 * (size_t)L.Mp) : 0;
+  L.cmaxB = acc ? take(4 * (size_t)L.Np) : 0;
+  L.barA = acc ? take((size_t)L.Mp * L.Kp) : 0;
+  L.barB = acc ? take((size_t)L.Np * L.Kp) : 0;
   L.RA = take((size_t)N * L.Mp * L.Kp);
   L.RB = take((size_t)N * L.Np * L.Kp);
   L.U = take((size_t)N * L.Mp * L.Np);
@@ -194,7 +205,7 @@ struct Debug {
 template <typename T, int LIMBS>
 void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, int64_t n,
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
-  dim3 gA((unsigned)(L.Mp / 64), (unsigned)(L.Kp / 128));
+  dim3 gA((unsigned)(L.Mp / 256), (unsigned)(L.Kp / 128));
   k2_split_strided<T, LIMBS><<<gA, 256, 0, g_stream>>>(
       A, lda, m, k, (const int32_t*)(ws + L.eA), tab, N, (int8_t*)(ws + L.RA), L.Mp, L.Kp);
   int64_t work = L.Np * (L.Kp / 16);
@@ -217,7 +228,6 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, N, mode, dbg == nullptr);
   if (rc) return rc;
   if (dbg && (dbg->t < 0 || dbg->t >= N)) return -10;
-  if (mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
   if (m == 0 || n == 0) return 0;
   int dev;
   if ((rc = ensure_device(&dev))) return rc;
@@ -250,12 +260,46 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
     int64_t work = n * L.nch;
     k1_partials_contig<T><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
         B, ldb, n, k, L.nch, (double*)(ws + L.partB), pmB);
-    k1_fold<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
-        (double*)(ws + L.partA), pmA, L.nch, m, mode, tab, (int32_t*)(ws + L.eA),
-        (double*)(ws + L.SA), (int*)(ws + L.status));
-    k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
-        (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
-        (double*)(ws + L.SB), (int*)(ws + L.status));
+    if (mode != OZ2_MODE_ACCURATE) {
+      k1_fold<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partA), pmA, L.nch, m, mode, tab, (int32_t*)(ws + L.eA),
+          (double*)(ws + L.SA), (int*)(ws + L.status));
+      k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
+          (double*)(ws + L.SB), (int*)(ws + L.status));
+    } else {
+      // Accurate mode (Section 2.3): first scale from the maxima, bar
+      // matrices, one INT8 GEMM reduced to row/column maxima, exponents.
+      int32_t* e1A = (int32_t*)(ws + L.e1A);
+      int32_t* e1B = (int32_t*)(ws + L.e1B);
+      k1_fold_first<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partA), pmA, L.nch, m, e1A, (int*)(ws + L.status));
+      k1_fold_first<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partB), pmB, L.nch, n, e1B, (int*)(ws + L.status));
+      dim3 gb((unsigned)(L.Mp / 256), (unsigned)(L.Kp / 128));
+      k2_bar_strided<T><<<gb, 256, 0, g_stream>>>(A, lda, m, k, e1A, (int8_t*)(ws + L.barA),
+                                                  L.Mp, L.Kp);
+      int64_t wb = L.Np * (L.Kp / 16);
+      k2_bar_contig<T><<<(unsigned)((wb + 255) / 256), 256, 0, g_stream>>>(
+          B, ldb, n, k, e1B, (int8_t*)(ws + L.barB), L.Np, L.Kp);
+      int32_t* cmA = (int32_t*)(ws + L.cmaxA);
+      int32_t* cmB = (int32_t*)(ws + L.cmaxB);
+      k_fill_i32<<<(unsigned)((L.Mp + 255) / 256), 256, 0, g_stream>>>(cmA, L.Mp, 0);
+      k_fill_i32<<<(unsigned)((L.Np + 255) / 256), 256, 0, g_stream>>>(cmB, L.Np, 0);
+      const int tiles1 = (int)((L.Mp / kBM) * (L.Np / kBN));
+      k3_gemm_i8<kBM, kBN, kBK, 2><<<(unsigned)tiles1, 256, 0, g_stream>>>(
+          (const int8_t*)(ws + L.barA), (const int8_t*)(ws + L.barB), nullptr, cmA, cmB, m, n,
+          L.Mp, L.Np, L.Kp, tab, 0);
+      k1_accurate_exponent<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+          e1A, cmA, m, tab, (int32_t*)(ws + L.eA));
+      k1_accurate_exponent<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+          e1B, cmB, n, tab, (int32_t*)(ws + L.eB));
+      // no squared norms in this mode: report zeros
+      k_fill_i32<<<(unsigned)((2 * m + 255) / 256), 256, 0, g_stream>>>((int32_t*)(ws + L.SA),
+                                                                         2 * m, 0);
+      k_fill_i32<<<(unsigned)((2 * n + 255) / 256), 256, 0, g_stream>>>((int32_t*)(ws + L.SB),
+                                                                         2 * n, 0);
+    }
   }
   clk.mark(1);
   // K2: integers and residues.
@@ -269,13 +313,13 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   const int tiles = (int)((L.Mp / kBM) * (L.Np / kBN));
   if (dbg) {
     if (dbg->Ct)
-      k3_gemm_i8<kBM, kBN, kBK, true><<<(unsigned)tiles, 256, 0, g_stream>>>(
-          (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr, dbg->Ct, m, n, L.Mp,
-          L.Np, L.Kp, tab, dbg->t);
+      k3_gemm_i8<kBM, kBN, kBK, 1><<<(unsigned)tiles, 256, 0, g_stream>>>(
+          (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr, dbg->Ct, nullptr, m,
+          n, L.Mp, L.Np, L.Kp, tab, dbg->t);
   } else {
-    k3_gemm_i8<kBM, kBN, kBK, false><<<(unsigned)(tiles * N), 256, 0, g_stream>>>(
+    k3_gemm_i8<kBM, kBN, kBK, 0><<<(unsigned)(tiles * N), 256, 0, g_stream>>>(
         (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), (uint8_t*)(ws + L.U), nullptr,
-        m, n, L.Mp, L.Np, L.Kp, tab, 0);
+        nullptr, m, n, L.Mp, L.Np, L.Kp, tab, 0);
   }
   clk.mark(3);
   // K4: CRT and unscaling.
@@ -311,9 +355,246 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Batched path: graph built once per batch signature, replayed per call.
+// ---------------------------------------------------------------------------
+
+struct BatchState {
+  bool valid = false;
+  uint64_t sig = 0;
+  int dev = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+  BatchProb* h_probs = nullptr;   // pinned host copy of the descriptors
+  size_t h_cap = 0;
+  char* meta = nullptr;           // device: counter, status, descriptors, prefixes, items
+  size_t meta_bytes = 0;
+};
+BatchState g_batch;
+
+uint64_t mix64(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+void batch_release() {
+  if (g_batch.exec) (void)hipGraphExecDestroy(g_batch.exec);
+  if (g_batch.graph) (void)hipGraphDestroy(g_batch.graph);
+  g_batch.exec = nullptr;
+  g_batch.graph = nullptr;
+  g_batch.valid = false;
+}
+
+int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
+  if (bad) *bad = -1;
+  if (batch < 0) return -1;
+  if (batch > 0 && !P) return -2;
+  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL) return -3;
+  if (batch > 65535) return OZ2_ERR_TOO_LARGE;
+  for (int i = 0; i < batch; ++i) {
+    const oz2_problem& q = P[i];
+    int rc = check_args(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, q.N, mode, true);
+    if (!rc && q.reserved != 0) rc = -12;
+    if (!rc && (q.m > 65535 * (int64_t)kBatchTile || q.n > 65535 * (int64_t)kBatchTile))
+      rc = OZ2_ERR_TOO_LARGE;
+    if (rc) {
+      if (bad) *bad = i;
+      return rc;
+    }
+  }
+  if (batch == 0) return 0;
+  int dev, rc;
+  if ((rc = ensure_device(&dev))) return rc;
+  build_host_tables();
+  DevState& D = g_dev[dev];
+
+  std::vector<int> act;
+  for (int i = 0; i < batch; ++i) {
+    const oz2_problem& q = P[i];
+    if (q.m == 0 || q.n == 0) continue;
+    if (q.k == 0) {
+      k_zero<double><<<(unsigned)((q.m * q.n + 255) / 256), 256, 0, g_stream>>>(q.C, q.m, q.n,
+                                                                            q.ldc);
+      continue;
+    }
+    if (!g_host_tables_ok[0][q.N]) return OZ2_ERR_UNSUPPORTED;
+    act.push_back(i);
+  }
+  if (act.empty()) return hipGetLastError() == hipSuccess ? 0 : OZ2_ERR_HIP;
+  const int na = (int)act.size();
+
+  // Per-problem workspace layouts (tile 128) inside the shared workspace.
+  std::vector<Layout> lay(na);
+  std::vector<size_t> base(na);
+  size_t total = 0;
+  int64_t nitems = 0;
+  uint64_t sig = mix64(0, (uint64_t)na);
+  sig = mix64(sig, (uint64_t)mode);
+  sig = mix64(sig, (uint64_t)dev);
+  for (int a = 0; a < na; ++a) {
+    const oz2_problem& q = P[act[a]];
+    lay[a] = make_layout(q.m, q.n, q.k, q.N, mode, kBatchTile);
+    base[a] = total;
+    total += lay[a].total;
+    nitems += (int64_t)q.N * (lay[a].Mp / kBatchTile) * (lay[a].Np / kBatchTile);
+    sig = mix64(mix64(mix64(mix64(sig, (uint64_t)q.m), (uint64_t)q.n), (uint64_t)q.k),
+                (uint64_t)q.N);
+  }
+  if (nitems > INT32_MAX) return OZ2_ERR_TOO_LARGE;
+  char* ws = nullptr;
+  if ((rc = get_workspace(dev, total, &ws))) return rc;
+
+  // Metadata layout in the batch-owned device allocation.
+  const size_t off_counter = 0, off_status = 256, off_probs = 512;
+  const size_t off_prefix = off_probs + align256(sizeof(BatchProb) * na);
+  const size_t off_items = off_prefix + align256(sizeof(int64_t) * (na + 1) * kB_NSTAGES);
+  const size_t meta_need = off_items + align256(sizeof(WorkItem) * (size_t)nitems);
+  int64_t blocks[kB_NSTAGES];
+
+  if (!g_batch.valid || g_batch.sig != sig || g_batch.dev != dev) {
+    if (g_batch.launched) (void)hipEventSynchronize(g_batch.done);
+    batch_release();
+    if (!g_batch.cap && hipStreamCreateWithFlags(&g_batch.cap, hipStreamNonBlocking) != hipSuccess)
+      return OZ2_ERR_HIP;
+    if (!g_batch.done && hipEventCreateWithFlags(&g_batch.done, hipEventDisableTiming) != hipSuccess)
+      return OZ2_ERR_HIP;
+    if (g_batch.meta_bytes < meta_need) {
+      if (g_batch.meta) (void)hipFree(g_batch.meta);
+      g_batch.meta = nullptr;
+      g_batch.meta_bytes = 0;
+      if (hipMalloc(&g_batch.meta, meta_need) != hipSuccess) return OZ2_ERR_WORKSPACE;
+      g_batch.meta_bytes = meta_need;
+    }
+    if (g_batch.h_cap < (size_t)na) {
+      if (g_batch.h_probs) (void)hipHostFree(g_batch.h_probs);
+      g_batch.h_probs = nullptr;
+      g_batch.h_cap = 0;
+      if (hipHostMalloc((void**)&g_batch.h_probs, sizeof(BatchProb) * na, 0) != hipSuccess)
+        return OZ2_ERR_WORKSPACE;
+      g_batch.h_cap = na;
+    }
+    // Block prefix sums per stage and the GEMM work list (largest k first).
+    std::vector<int64_t> prefix((size_t)(na + 1) * kB_NSTAGES, 0);
+    for (int st = 0; st < kB_NSTAGES; ++st) {
+      int64_t acc = 0;
+      for (int a = 0; a < na; ++a) {
+        const oz2_problem& q = P[act[a]];
+        const Layout& L = lay[a];
+        int64_t c = 0;
+        switch (st) {
+          case kB_K1A: c = ((q.m + 63) / 64) * ((L.nch + 3) / 4); break;
+          case kB_K1B: c = (q.n * L.nch + 255) / 256; break;
+          case kB_FOLDA: c = (q.m + 255) / 256; break;
+          case kB_FOLDB: c = (q.n + 255) / 256; break;
+          case kB_K2A: c = ((L.Mp + 255) / 256) * (L.Kp / 128); break;
+          case kB_K2B: c = (L.Np * (L.Kp / 16) + 255) / 256; break;
+          default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
+        }
+        prefix[(size_t)st * (na + 1) + a] = acc;
+        acc += c;
+      }
+      prefix[(size_t)st * (na + 1) + na] = acc;
+      blocks[st] = acc;
+      if (acc > INT32_MAX) return OZ2_ERR_TOO_LARGE;
+    }
+    std::vector<int> order(na);
+    for (int a = 0; a < na; ++a) order[a] = a;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return P[act[x]].k > P[act[y]].k; });
+    std::vector<WorkItem> items;
+    items.reserve((size_t)nitems);
+    for (int a : order) {
+      const oz2_problem& q = P[act[a]];
+      const int tmn = (int)(lay[a].Mp / kBatchTile), tnn = (int)(lay[a].Np / kBatchTile);
+      for (int t = 0; t < q.N; ++t)
+        for (int tn = 0; tn < tnn; ++tn)
+          for (int tm = 0; tm < tmn; ++tm)
+            items.push_back(WorkItem{(uint16_t)a, (uint16_t)t, (uint16_t)tm, (uint16_t)tn});
+    }
+    if (hipMemcpyAsync(g_batch.meta + off_prefix, prefix.data(), prefix.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice, g_stream) != hipSuccess ||
+        hipMemcpyAsync(g_batch.meta + off_items, items.data(), items.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice, g_stream) != hipSuccess ||
+        hipStreamSynchronize(g_stream) != hipSuccess)
+      return OZ2_ERR_HIP;
+
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t gemm_grid = std::min<int64_t>(nitems, (int64_t)cus * 2);
+
+    // Capture: reset counter/status, refresh descriptors, stages, GEMM, CRT.
+    hipStream_t cs = g_batch.cap;
+    BatchProb* d_probs = (BatchProb*)(g_batch.meta + off_probs);
+    const int64_t* d_prefix = (const int64_t*)(g_batch.meta + off_prefix);
+    int* d_counter = (int*)(g_batch.meta + off_counter);
+    int* d_status = (int*)(g_batch.meta + off_status);
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return OZ2_ERR_HIP;
+    kb_reset<<<1, 64, 0, cs>>>(d_counter, d_status);
+    (void)hipMemcpyAsync(d_probs, g_batch.h_probs, sizeof(BatchProb) * na, hipMemcpyHostToDevice,
+                         cs);
+    for (int st = 0; st < kB_K4; ++st)
+      if (blocks[st] > 0)
+        kb_stage<<<(unsigned)blocks[st], 256, 0, cs>>>(d_probs, d_prefix, na, st, d_status);
+    kb_gemm<<<(unsigned)gemm_grid, 256, 0, cs>>>(d_probs, (const WorkItem*)(g_batch.meta + off_items),
+                                                 (int)nitems, d_counter);
+    kb_stage<<<(unsigned)blocks[kB_K4], 256, 0, cs>>>(d_probs, d_prefix, na, kB_K4, d_status);
+    hipError_t e1 = hipStreamEndCapture(cs, &g_batch.graph);
+    if (e1 != hipSuccess || !g_batch.graph) return OZ2_ERR_HIP;
+    if (hipGraphInstantiate(&g_batch.exec, g_batch.graph, nullptr, nullptr, 0) != hipSuccess)
+      return OZ2_ERR_HIP;
+    g_batch.sig = sig;
+    g_batch.dev = dev;
+    g_batch.valid = true;
+  }
+
+  // Refresh the descriptors (pointers and workspace regions) for this call.
+  if (g_batch.launched && hipEventSynchronize(g_batch.done) != hipSuccess) return OZ2_ERR_HIP;
+  const int acc_tab = 0;
+  for (int a = 0; a < na; ++a) {
+    const oz2_problem& q = P[act[a]];
+    const Layout& L = lay[a];
+    char* w = ws + base[a];
+    BatchProb& B = g_batch.h_probs[a];
+    B.A = q.A;
+    B.B = q.B;
+    B.C = q.C;
+    B.m = q.m; B.n = q.n; B.k = q.k;
+    B.lda = q.lda; B.ldb = q.ldb; B.ldc = q.ldc;
+    B.Mp = L.Mp; B.Np = L.Np; B.Kp = L.Kp; B.nch = L.nch;
+    B.N = q.N;
+    B.mode = mode;
+    B.tab = D.d_tables + acc_tab * (kMaxN + 1) + q.N;
+    B.eA = (int32_t*)(w + L.eA);
+    B.eB = (int32_t*)(w + L.eB);
+    B.partA = (double*)(w + L.partA);
+    B.partB = (double*)(w + L.partB);
+    B.maxA = L.maxA ? (double*)(w + L.maxA) : nullptr;
+    B.maxB = L.maxB ? (double*)(w + L.maxB) : nullptr;
+    B.SA = (double*)(w + L.SA);
+    B.SB = (double*)(w + L.SB);
+    B.RA = (int8_t*)(w + L.RA);
+    B.RB = (int8_t*)(w + L.RB);
+    B.U = (uint8_t*)(w + L.U);
+    B.k1a_gx = (q.m + 63) / 64;
+  }
+  if (hipGraphLaunch(g_batch.exec, g_stream) != hipSuccess) return OZ2_ERR_HIP;
+  if (hipEventRecord(g_batch.done, g_stream) != hipSuccess) return OZ2_ERR_HIP;
+  g_batch.launched = true;
+  return hipGetLastError() == hipSuccess ? 0 : OZ2_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
+
+int ozaki2_dgemm_batched(int batch, const oz2_problem* problems, int mode, int* bad_index) {
+  return run_batched(batch, problems, mode, bad_index);
+}
+
 
 int ozaki2_dgemm(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
                  const double* B, int64_t ldb, double* C, int64_t ldc, int N, int mode) {
@@ -355,7 +636,8 @@ int ozaki2_get_device_status(int* status) {
   if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
   // The status word lives at offset 0 of whichever workspace the last call
   // used; both candidates are checked and cleared.
-  void* cands[2] = {g_user_ws, g_dev[dev].ws};
+  void* cands[3] = {g_user_ws, g_dev[dev].ws,
+                    g_batch.meta ? (void*)(g_batch.meta + 256) : nullptr};
   for (void* p : cands) {
     if (!p) continue;
     int v = 0;
@@ -386,6 +668,13 @@ const char* ozaki2_version(void) {
 
 int ozaki2_finalize(void) {
   (void)hipStreamSynchronize(g_stream);
+  if (g_batch.launched) (void)hipEventSynchronize(g_batch.done);
+  batch_release();
+  if (g_batch.meta) (void)hipFree(g_batch.meta);
+  if (g_batch.h_probs) (void)hipHostFree(g_batch.h_probs);
+  if (g_batch.done) (void)hipEventDestroy(g_batch.done);
+  if (g_batch.cap) (void)hipStreamDestroy(g_batch.cap);
+  g_batch = BatchState();
   for (auto& tc : g_pending) g_free.push_back(tc);
   g_pending.clear();
   for (auto& tc : g_free)

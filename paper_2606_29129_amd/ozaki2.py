@@ -26,6 +26,13 @@ _lib = None
 
 _c_i64, _c_int, _vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
 
+
+class Oz2Problem(ctypes.Structure):
+    """struct oz2_problem of include/ozaki2.h."""
+    _fields_ = [("m", _c_i64), ("n", _c_i64), ("k", _c_i64), ("A", _vp), ("lda", _c_i64),
+                ("B", _vp), ("ldb", _c_i64), ("C", _vp), ("ldc", _c_i64), ("N", _c_int),
+                ("reserved", _c_int)]
+
 _SIGS = {
     "ozaki2_dgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
     "ozaki2_sgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
@@ -44,6 +51,8 @@ _SIGS = {
     "ozaki2_debug_stages": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _c_int, _c_int, _c_int]
                             + [_vp] * 7, _c_int),
     "ozaki2_debug_log2f": ([_vp, _vp, _c_i64], _c_int),
+    "ozaki2_dgemm_batched": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int, ctypes.POINTER(_c_int)],
+                             _c_int),
 }
 
 
@@ -159,6 +168,21 @@ def ozaki2_debug_stages(m, n, k, A, lda, B, ldb, N, mode, t,
                                      _ptr(RB), _ptr(Ct))
 
 
+def ozaki2_dgemm_batched(problems, mode=MODE_REVISED):
+    """problems: a sequence of Oz2Problem (or of tuples with its fields, pointers
+    as tensors or ints).  Returns (rc, bad_index)."""
+    arr = (Oz2Problem * max(1, len(problems)))()
+    for i, q in enumerate(problems):
+        if isinstance(q, Oz2Problem):
+            arr[i] = q
+        else:
+            m, n, k, A, lda, B, ldb, C, ldc, N = q
+            arr[i] = Oz2Problem(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, 0)
+    bad = ctypes.c_int(-1)
+    rc = lib().ozaki2_dgemm_batched(len(problems), arr, mode, ctypes.byref(bad))
+    return rc, bad.value
+
+
 def ozaki2_debug_log2f(x, y, n):
     return lib().ozaki2_debug_log2f(_ptr(x), _ptr(y), n)
 
@@ -207,3 +231,25 @@ def _gemm(A, B, N, mode, out, fn):
     rc = fn(n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), N, _mode(mode))
     _check(fn.__name__, rc)
     return C
+
+
+def dgemm_batched(pairs, N, mode="revised"):
+    """C_i = A_i @ B_i for a list of row-major float64 CUDA tensor pairs, in one
+    batched call; N is an int or a list with one moduli count per problem."""
+    import torch
+    Ns = [N] * len(pairs) if isinstance(N, int) else list(N)
+    outs, probs = [], []
+    for (A, B), Ni in zip(pairs, Ns):
+        A = A.contiguous()
+        B = B.contiguous()
+        m, k = A.shape
+        n = B.shape[1]
+        C = torch.empty((m, n), dtype=torch.float64, device=A.device)
+        outs.append((A, B, C))
+        # row-major C = A B is column-major C^T = B^T A^T
+        probs.append((n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), Ni))
+    _bind_current_stream(torch)
+    rc, bad = ozaki2_dgemm_batched(probs, _mode(mode))
+    if rc:
+        raise Ozaki2Error(f"ozaki2_dgemm_batched (problem {bad})", rc)
+    return [c for _, _, c in outs]

@@ -267,3 +267,21 @@ def test_sgemm_parity(m, n, k, phi, N):
     want = ref.sgemm(A32, B32, N)
     got = _gpu_sgemm(A32, B32, N)
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("m,n,k,phi,N,seed", [(300, 280, 520, 1.0, 14, 31), (37, 90, 129, 4.0, 20, 32),
+                                              (64, 48, 33, 0.5, 8, 33)])
+def test_accurate_mode_parity(m, n, k, phi, N, seed):
+    """Accurate mode (Section 2.3): the scale estimate from the INT8 product
+    of the bar matrices; exponents, residues, products and C equal the oracle
+    bit for bit."""
+    A, B = inputs.problem(m, n, k, phi, seed)
+    A[5, :] = 0.0
+    r = ref.gemm(A, B, N, ref.ACCURATE)
+    g = _gpu_stages(A, B, N, 2, N - 1)
+    assert list(g["eA"]) == r["e_rows"] and list(g["eB"]) == r["e_cols"]
+    for t in (0, N - 1):
+        assert np.array_equal(g["RA"][t], r["RA"][t])
+        assert np.array_equal(g["RB"][t], r["RB"][t].T)
+    assert np.array_equal(g["Ct"].astype(np.int64), r["G"][N - 1])
+    assert _bits_equal(_gpu_dgemm(A, B, N, mode=2), r["C"])
