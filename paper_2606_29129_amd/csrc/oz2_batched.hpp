@@ -34,6 +34,9 @@ struct BatchProb {
   int64_t k1a_gx;  // K1 strided grid width (height is ceil(nch/4))
 };
 
+// The fast modes need at most 3 limbs of 26 bits for |a'| (< 2^78 at N = 20).
+constexpr int kBatchLimbs = 3;
+
 // Stages with a per-problem block count.
 enum BatchStage { kB_K1A = 0, kB_K1B, kB_FOLDA, kB_FOLDB, kB_K2A, kB_K2B, kB_K4, kB_NSTAGES };
 
@@ -49,15 +52,18 @@ __device__ __forceinline__ int find_problem(const int64_t* __restrict__ prefix, 
   return lo;
 }
 
+// One instantiation per stage, so that each gets the register budget (and
+// occupancy) of its own body.
+template <int STAGE>
 __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ probs,
                                                 const int64_t* __restrict__ prefix, int batch,
-                                                int stage, int* __restrict__ status) {
-  const int64_t* pre = prefix + (int64_t)stage * (batch + 1);
+                                                int* __restrict__ status) {
+  const int64_t* pre = prefix + (int64_t)STAGE * (batch + 1);
   const int64_t b = blockIdx.x;
   const int p = find_problem(pre, batch, b);
   const int64_t local = b - pre[p];
   const BatchProb& P = probs[p];
-  switch (stage) {
+  switch (STAGE) {
     case kB_K1A: {
       int64_t bx = local % P.k1a_gx, by = local / P.k1a_gx;
       k1_partials_strided_body<double>(P.A, P.lda, P.m, P.k, P.nch, P.partA, P.maxA, bx, by);
@@ -73,14 +79,14 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
       k1_fold_body(P.partB, P.maxB, P.nch, P.n, P.mode, P.tab, P.eB, P.SB, status, local);
       break;
     case kB_K2A: {
-      const int64_t gx = (P.Mp + 255) / 256;
+      const int64_t gx = P.Mp / 64;
       int64_t bx = local % gx, by = local / gx;
-      k2_split_strided_body<double, 4>(P.A, P.lda, P.m, P.k, P.eA, P.tab, P.N, P.RA, P.Mp,
+      k2_split_strided_body<double, kBatchLimbs>(P.A, P.lda, P.m, P.k, P.eA, P.tab, P.N, P.RA, P.Mp,
                                        P.Kp, bx, by);
       break;
     }
     case kB_K2B:
-      k2_split_contig_body<double, 4>(P.B, P.ldb, P.n, P.k, P.eB, P.tab, P.N, P.RB, P.Np, P.Kp,
+      k2_split_contig_body<double, kBatchLimbs>(P.B, P.ldb, P.n, P.k, P.eB, P.tab, P.N, P.RB, P.Np, P.Kp,
                                       local);
       break;
     default:

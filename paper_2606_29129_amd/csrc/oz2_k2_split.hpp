@@ -96,28 +96,62 @@ __device__ __forceinline__ void split16_store(const double (&a)[16], int32_t e,
 }
 
 // Strided vectors (rows of column-major A): entry h of vector v at
-// X[v + h ld].  A block of 256 lanes covers 256 vectors x 128 entries; lane =
-// vector, so every load instruction reads 64 consecutive entries of one
-// column (512 contiguous bytes), and each lane converts its 128 entries in
-// 8 groups of 16, writing one whole 128-byte line per plane.
+// X[v + h ld].  A block covers 64 vectors x 128 entries: lane = vector, so
+// every load instruction reads 64 consecutive entries of one column (512
+// contiguous bytes); wave w converts entries [32w, 32w + 32) in two groups of
+// 16.  Per plane the 64 x 128 residue bytes are staged in LDS (rows padded to
+// 144 bytes: conflict-free 16-byte writes, double-buffered: one barrier per
+// plane) and written out as whole 128-byte rows.
 template <typename T, int LIMBS>
 __device__ __forceinline__ void k2_split_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
     int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx, int64_t by) {
-  const int64_t v = bx * 256 + threadIdx.x;
-  if (v >= Vp) return;
+  __shared__ uint4 stage[2][64][9];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t v0 = bx * 64, hb = by * 128;
+  const int64_t v = v0 + lane;
   const int32_t ev = v < nvec ? e[v] : 0;
-  const int64_t plane = Vp * Kp;
-  const int64_t hb = by * 128;
-#pragma unroll 1
-  for (int g = 0; g < 8; ++g) {
-    const int64_t h0 = hb + g * 16;
+  Limbs<LIMBS> L[2][16];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int64_t h0 = hb + wave * 32 + g * 16;
     double a[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
       a[i] = (v < nvec && h0 + i < k) ? (double)X[v + (h0 + i) * ld] : 0.0;
-    split16_store<LIMBS>(a, ev, tab, N, R + v * Kp + h0, plane);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) L[g][i] = make_limbs<LIMBS>(a[i], ev);
+  }
+  const int64_t plane = Vp * Kp;
+  const int orow = threadIdx.x >> 3, ochunk = threadIdx.x & 7;  // write-out mapping
+  for (int t = 0; t < N; ++t) {
+    const int sb = t & 1;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const Limbs<LIMBS>& x = L[g][4 * q + i];
+          const int r = (t == 0) ? residue_256<LIMBS>(x)
+                                 : residue_odd<LIMBS>(x, tab->pow26[t], tab->p[t], tab->inv_p[t]);
+          b |= (uint32_t)(uint8_t)(int8_t)r << (8 * i);
+        }
+        w[q] = b;
+      }
+      stage[sb][lane][wave * 2 + g] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int row = pass * 32 + orow;
+      if (v0 + row < Vp)
+        *reinterpret_cast<uint4*>(R + (int64_t)t * plane + (v0 + row) * Kp + hb + ochunk * 16) =
+            stage[sb][row][ochunk];
+    }
   }
 }
 

@@ -66,7 +66,49 @@ __device__ __forceinline__ void tile_of(int id, int total, int tiles_m, int tile
   *tn = in / gm;
 }
 
+// Global -> LDS copy of 16 bytes per lane without a register round trip
+// (global_load_lds_dwordx4): lane l of the wave writes dst + 16 l, dst being
+// wave-uniform.  The asm waits carry a memory clobber so that the compiler
+// does not move LDS reads across them.
+__device__ __forceinline__ void load_lds16(const int8_t* src, int8_t* dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+#endif
+}
+__device__ __forceinline__ void wait_vmem_all() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#endif
+}
+
 // One BM x BN output tile of plane t (tile row tm, tile column tn).
+//
+// Main loop (one 128-byte k slab per iteration, two LDS buffers):
+//   wait for this wave's loads of slab kt, barrier (slab kt is in LDS for
+//   every wave, and the buffer of slab kt-1 is free), then for each of the
+//   four 32-byte k steps: read the next step's fragments, issue a quarter of
+//   slab kt+1's global->LDS loads, and run the TM x TN MFMAs, interleaved by
+//   scheduling groups so that memory instructions never queue up in front of
+//   the matrix core.  Lane l of wave w in load round i fills LDS slot
+//   16 (i 256 + 64 w + l); the slot's row and swizzled chunk decide which 16
+//   source bytes it fetches.
+// Scheduling groups for one MFMA k step: NL global loads, NM MFMAs and ND
+// LDS fragment reads interleaved as NL groups of
+// {DS read, MFMA, DS read, VMEM read, MFMA}.
+template <int NL, int NM, int ND>
+__device__ __forceinline__ void sched_k_step() {
+  static_assert(NM % (2 * NL) == 0 && ND % NL == 0, "group shape");
+#pragma unroll
+  for (int g = 0; g < NL; ++g) {
+    if constexpr (ND / NL / 2 > 0) __builtin_amdgcn_sched_group_barrier(0x100, ND / NL / 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, NM / NL / 2, 0);
+    if constexpr (ND / NL - ND / NL / 2 > 0)
+      __builtin_amdgcn_sched_group_barrier(0x100, ND / NL - ND / NL / 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, NM / NL / 2, 0);
+  }
+}
+
 template <int BM, int BN, int BK, int EPI>
 __device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
@@ -77,7 +119,9 @@ __device__ __forceinline__ void gemm_tile(
   constexpr int TM = BM / 64, TN = BN / 64;      // 32x32 blocks per wave
   constexpr int CH = BK / 16;                    // 16-byte chunks per row
   constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
+  constexpr int KS = BK / 32;                    // MFMA k steps per slab
   static_assert(A_LOADS * 256 == BM * CH && B_LOADS * 256 == BN * CH, "tile");
+  static_assert((A_LOADS + B_LOADS) % KS == 0, "loads per k step");
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -91,35 +135,30 @@ __device__ __forceinline__ void gemm_tile(
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = v16i{0};
 
-  v4i ra[A_LOADS], rb[B_LOADS];
-  auto gload = [&](int64_t k0) {
+  // Source offset of each of this lane's load slots (fixed across slabs).
+  int64_t offA[A_LOADS], offB[B_LOADS];
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) {
-      int id = tid + 256 * i, row = id / CH, ch = id % CH;
-      ra[i] = *reinterpret_cast<const v4i*>(gA + (int64_t)row * Kp + k0 + ch * 16);
-    }
+  for (int i = 0; i < A_LOADS; ++i) {
+    const int s = i * 256 + tid, row = s / CH;
+    offA[i] = (int64_t)row * Kp + swz_chunk<BK>(row, s % CH) * 16;  // XOR: an involution
+  }
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) {
-      int id = tid + 256 * i, row = id / CH, ch = id % CH;
-      rb[i] = *reinterpret_cast<const v4i*>(gB + (int64_t)row * Kp + k0 + ch * 16);
-    }
-  };
-  auto lstore = [&](int buf) {
-    int8_t* sA = lds[buf];
-    int8_t* sB = lds[buf] + BM * BK;
+  for (int i = 0; i < B_LOADS; ++i) {
+    const int s = i * 256 + tid, row = s / CH;
+    offB[i] = (int64_t)row * Kp + swz_chunk<BK>(row, s % CH) * 16;
+  }
+  // Loads of slab k0 into buffer buf, rounds with index = part (mod parts).
+  auto gload = [&](int buf, int64_t k0, int part, int parts) {
 #pragma unroll
-    for (int i = 0; i < A_LOADS; ++i) {
-      int id = tid + 256 * i, row = id / CH, ch = id % CH;
-      *reinterpret_cast<v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16) = ra[i];
-    }
+    for (int i = 0; i < A_LOADS; ++i)
+      if (i % parts == part) load_lds16(gA + offA[i] + k0, lds[buf] + (i * 256 + wave * 64) * 16);
 #pragma unroll
-    for (int i = 0; i < B_LOADS; ++i) {
-      int id = tid + 256 * i, row = id / CH, ch = id % CH;
-      *reinterpret_cast<v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16) = rb[i];
-    }
+    for (int i = 0; i < B_LOADS; ++i)
+      if ((A_LOADS + i) % parts == part)
+        load_lds16(gB + offB[i] + k0, lds[buf] + BM * BK + (i * 256 + wave * 64) * 16);
   };
 
-  // Fragment reads for k-step kk of LDS buffer buf into register set F.
+  // Fragment reads for k step kk of LDS buffer buf into register set F.
   v4i fa[2][TM], fb[2][TN];
   auto fload = [&](int buf, int kk, int F) {
     const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
@@ -144,29 +183,32 @@ __device__ __forceinline__ void gemm_tile(
         acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
   };
 
-  // Pipeline: the global loads of tile kt+1 are in flight during all of
-  // tile kt; the LDS fragment reads of step kk+1 are in flight during the
-  // MFMAs of step kk (register double buffer); the next tile's first
-  // fragments are read right after the barrier that publishes it.
-  constexpr int KS = BK / 32;
   const int nk = (int)(Kp / BK);
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  if (nk > 1) gload(BK);
-  fload(0, 0, 0);
+  gload(0, 0, 0, 1);
+  int buf = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
+    wait_vmem_all();
+    __syncthreads();
+    // The next slab's loads are issued unconditionally (the last iteration
+    // re-fetches the last slab into the idle buffer, which is never read) so
+    // that the whole slab is one basic block the scheduling groups can shape.
+    const int64_t knext = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
+    fload(buf, 0, 0);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       if (kk + 1 < KS) fload(buf, kk + 1, (kk + 1) & 1);
+      gload(buf ^ 1, knext, kk, KS);
       mfmas(kk & 1);
+      // Inside one k step: the TM x TN independent MFMAs with the next step's
+      // TM + TN fragment reads and the step's share of the global loads
+      // spread among them; nothing crosses into the neighbouring steps.
+      if (kk + 1 < KS) sched_k_step<(A_LOADS + B_LOADS) / KS, TM * TN, TM + TN>();
+      else             sched_k_step<(A_LOADS + B_LOADS) / KS, TM * TN, 0>();
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
-    if (kt + 2 < nk) gload((int64_t)(kt + 2) * BK);
-    if (kt + 1 < nk) fload(buf ^ 1, 0, 0);
+    buf ^= 1;
   }
+  wait_vmem_all();  // no load may still target LDS when the tile returns
 
   const int64_t Mb = Mp / 32;
   if constexpr (EPI == 1) {

@@ -205,7 +205,7 @@ struct Debug {
 template <typename T, int LIMBS>
 void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, int64_t n,
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
-  dim3 gA((unsigned)(L.Mp / 256), (unsigned)(L.Kp / 128));
+  dim3 gA((unsigned)(L.Mp / 64), (unsigned)(L.Kp / 128));
   k2_split_strided<T, LIMBS><<<gA, 256, 0, g_stream>>>(
       A, lda, m, k, (const int32_t*)(ws + L.eA), tab, N, (int8_t*)(ws + L.RA), L.Mp, L.Kp);
   int64_t work = L.Np * (L.Kp / 16);
@@ -420,7 +420,8 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
                                                                             q.ldc);
       continue;
     }
-    if (!g_host_tables_ok[0][q.N]) return OZ2_ERR_UNSUPPORTED;
+    if (!g_host_tables_ok[0][q.N] || g_host_tables[0][q.N].limbs > kBatchLimbs)
+      return OZ2_ERR_UNSUPPORTED;
     act.push_back(i);
   }
   if (act.empty()) return hipGetLastError() == hipSuccess ? 0 : OZ2_ERR_HIP;
@@ -489,7 +490,7 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
           case kB_K1B: c = (q.n * L.nch + 255) / 256; break;
           case kB_FOLDA: c = (q.m + 255) / 256; break;
           case kB_FOLDB: c = (q.n + 255) / 256; break;
-          case kB_K2A: c = ((L.Mp + 255) / 256) * (L.Kp / 128); break;
+          case kB_K2A: c = (L.Mp / 64) * (L.Kp / 128); break;
           case kB_K2B: c = (L.Np * (L.Kp / 16) + 255) / 256; break;
           default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
         }
@@ -536,12 +537,19 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
     kb_reset<<<1, 64, 0, cs>>>(d_counter, d_status);
     (void)hipMemcpyAsync(d_probs, g_batch.h_probs, sizeof(BatchProb) * na, hipMemcpyHostToDevice,
                          cs);
-    for (int st = 0; st < kB_K4; ++st)
-      if (blocks[st] > 0)
-        kb_stage<<<(unsigned)blocks[st], 256, 0, cs>>>(d_probs, d_prefix, na, st, d_status);
+#define OZ2_STAGE(ST)                                                                   \
+  if (blocks[ST] > 0)                                                                   \
+    kb_stage<ST><<<(unsigned)blocks[ST], 256, 0, cs>>>(d_probs, d_prefix, na, d_status);
+    OZ2_STAGE(kB_K1A)
+    OZ2_STAGE(kB_K1B)
+    OZ2_STAGE(kB_FOLDA)
+    OZ2_STAGE(kB_FOLDB)
+    OZ2_STAGE(kB_K2A)
+    OZ2_STAGE(kB_K2B)
     kb_gemm<<<(unsigned)gemm_grid, 256, 0, cs>>>(d_probs, (const WorkItem*)(g_batch.meta + off_items),
                                                  (int)nitems, d_counter);
-    kb_stage<<<(unsigned)blocks[kB_K4], 256, 0, cs>>>(d_probs, d_prefix, na, kB_K4, d_status);
+    OZ2_STAGE(kB_K4)
+#undef OZ2_STAGE
     hipError_t e1 = hipStreamEndCapture(cs, &g_batch.graph);
     if (e1 != hipSuccess || !g_batch.graph) return OZ2_ERR_HIP;
     if (hipGraphInstantiate(&g_batch.exec, g_batch.graph, nullptr, nullptr, 0) != hipSuccess)

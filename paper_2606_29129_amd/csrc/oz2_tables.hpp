@@ -146,8 +146,9 @@ inline bool build_table(int N, bool accurate_limbs, ModTable* T) {
   const int pbits = P.bitlen();
   T->slices = (pbits + kSliceBits - 1) / kSliceBits;
   if (T->slices > kMaxSlices) return false;
-  // |a'| <= sqrt((P-1)/2) in the fast modes; accurate mode allows 64x more.
-  int abits = (pbits + 1) / 2 + 1 + (accurate_limbs ? 7 : 0);
+  // Fast modes: |a'| <= sqrt((P-1)/2) < 2^((pbits-1)/2), so pbits/2 bits
+  // suffice; accurate mode allows up to 64x more (bar entries <= 64).
+  int abits = pbits / 2 + (accurate_limbs ? 7 : 0);
   int limbs = (abits + kLimbBits - 1) / kLimbBits;
   T->limbs = limbs < 2 ? 2 : limbs;
   if (T->limbs > 4) return false;
