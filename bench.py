@@ -185,6 +185,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--traffic-calibration", type=int, default=0, metavar="BYTES",
+                    help="before the steps, run one torch.abs over a float64 tensor of "
+                         "BYTES bytes (the known-size kernel that scales rocprofv3 "
+                         "FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -218,6 +222,13 @@ def main():
     torch.cuda.synchronize()
     _log(f"inputs {m}x{k} and {k}x{n} generated in {time.time() - t0:.1f}s; "
          f"workspace {ws_bytes / 2**30:.2f} GiB")
+
+    if args.traffic_calibration:
+        src = torch.ones(args.traffic_calibration // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.abs(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         rc = oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, N, mode)

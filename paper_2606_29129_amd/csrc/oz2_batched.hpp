@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
       k1_fold_body(P.partB, P.maxB, P.nch, P.n, P.mode, P.tab, P.eB, P.SB, status, local);
       break;
     case kB_K2A: {
-      const int64_t gx = P.Mp / 64;
+      const int64_t gx = P.Mp / kK2VB;
       int64_t bx = local % gx, by = local / gx;
       k2_split_strided_body<double, kBatchLimbs>(P.A, P.lda, P.m, P.k, P.eA, P.tab, P.N, P.RA, P.Mp,
                                        P.Kp, bx, by);

@@ -15,7 +15,6 @@
 //
 // Output layout: plane t is a (Vp x Kp) int8 matrix, vector-major with the
 // k index contiguous (what the GEMM reads); padding rows and columns are 0.
-// Each lane converts 16 consecutive entries and stores 16 bytes per plane.
 #pragma once
 
 #include "oz2_k1_norm.hpp"
@@ -58,100 +57,82 @@ OZ2_HD int residue_256(const Limbs<LIMBS>& L) {
   return (int)(int8_t)(uint8_t)((int32_t)L.x[0] & 0xFF);
 }
 
-// Convert 16 entries of one vector and store their residues in all N planes.
-template <int LIMBS>
-__device__ __forceinline__ void split16_store(const double (&a)[16], int32_t e,
-                                              const ModTable* __restrict__ tab, int N,
-                                              int8_t* __restrict__ out, int64_t plane) {
-  Limbs<LIMBS> L[16];
+// Residues in plane t of EPT entries (limbs L), packed four to a dword in
+// entry order.
+template <int LIMBS, int EPT>
+__device__ __forceinline__ void pack_residues(const Limbs<LIMBS> (&L)[EPT], int t,
+                                              const ModTable* __restrict__ tab,
+                                              uint32_t (&w)[EPT / 4]) {
+  if (t == 0) {  // modulus 0 is 256
 #pragma unroll
-  for (int i = 0; i < 16; ++i) L[i] = make_limbs<LIMBS>(a[i], e);
-  // modulus 0 is 256
-  {
-    uint32_t w[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < EPT / 4; ++q) {
       uint32_t b = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) b |= ((uint32_t)(uint8_t)residue_256<LIMBS>(L[4 * q + i])) << (8 * i);
       w[q] = b;
     }
-    *reinterpret_cast<uint4*>(out) = make_uint4(w[0], w[1], w[2], w[3]);
-  }
-  for (int t = 1; t < N; ++t) {
-    const double p = tab->p[t];
-    const double ip = tab->inv_p[t];
+  } else {
+    const double p = tab->p[t], ip = tab->inv_p[t];
     const double* pw = tab->pow26[t];
-    uint32_t w[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < EPT / 4; ++q) {
       uint32_t b = 0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         b |= ((uint32_t)(uint8_t)(int8_t)residue_odd<LIMBS>(L[4 * q + i], pw, p, ip)) << (8 * i);
       w[q] = b;
     }
-    *reinterpret_cast<uint4*>(out + (int64_t)t * plane) = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
+template <int EPT>
+__device__ __forceinline__ void store_packed(int8_t* dst, const uint32_t (&w)[EPT / 4]) {
+  if constexpr (EPT == 4) *reinterpret_cast<uint32_t*>(dst) = w[0];
+  else if constexpr (EPT == 8) *reinterpret_cast<uint2*>(dst) = make_uint2(w[0], w[1]);
+  else *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Strided vectors (rows of column-major A): entry h of vector v at
-// X[v + h ld].  A block covers 64 vectors x 128 entries: lane = vector, so
-// every load instruction reads 64 consecutive entries of one column (512
-// contiguous bytes); wave w converts entries [32w, 32w + 32) in two groups of
-// 16.  Per plane the 64 x 128 residue bytes are staged in LDS (rows padded to
-// 144 bytes: conflict-free 16-byte writes, double-buffered: one barrier per
-// plane) and written out as whole 128-byte rows.
-template <typename T, int LIMBS>
+// X[v + h ld].  A block of 256 lanes covers VB vectors x (256 / VB) * 16
+// entries: lane = (vector tid % VB, entry group tid / VB), so each load
+// instruction reads VB consecutive entries of a column per group; every lane
+// converts 16 entries.  Per plane the block's residue bytes are staged in LDS
+// (rows padded by 16 bytes: conflict-free 16-byte writes; two buffers, one
+// barrier per plane) and written out as whole rows of (256 / VB) * 16 bytes.
+constexpr int kK2VB = 32;                       // vectors per strided block
+constexpr int kK2HB = (256 / kK2VB) * 16;       // entries per strided block
+
+template <typename T, int LIMBS, int VB = kK2VB>
 __device__ __forceinline__ void k2_split_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
     int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx, int64_t by) {
-  __shared__ uint4 stage[2][64][9];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t v0 = bx * 64, hb = by * 128;
-  const int64_t v = v0 + lane;
+  constexpr int G = 256 / VB, HB = G * 16;
+  static_assert(VB * G == 256 && (VB * HB / 16) == 256, "one write-out pass");
+  __shared__ uint4 stage[2][VB][G + 1];
+  const int vl = threadIdx.x % VB, g = threadIdx.x / VB;
+  const int64_t v0 = bx * VB, v = v0 + vl;
+  const int64_t h0 = by * HB + g * 16;
   const int32_t ev = v < nvec ? e[v] : 0;
-  Limbs<LIMBS> L[2][16];
-#pragma unroll
-  for (int g = 0; g < 2; ++g) {
-    const int64_t h0 = hb + wave * 32 + g * 16;
+  Limbs<LIMBS> L[16];
+  {
     double a[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
       a[i] = (v < nvec && h0 + i < k) ? (double)X[v + (h0 + i) * ld] : 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[g][i] = make_limbs<LIMBS>(a[i], ev);
+    for (int i = 0; i < 16; ++i) L[i] = make_limbs<LIMBS>(a[i], ev);
   }
   const int64_t plane = Vp * Kp;
-  const int orow = threadIdx.x >> 3, ochunk = threadIdx.x & 7;  // write-out mapping
+  const int orow = threadIdx.x / G, ochunk = threadIdx.x % G;  // write-out mapping
+  int8_t* out = R + (v0 + orow) * Kp + by * HB + ochunk * 16;
   for (int t = 0; t < N; ++t) {
     const int sb = t & 1;
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      uint32_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t b = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const Limbs<LIMBS>& x = L[g][4 * q + i];
-          const int r = (t == 0) ? residue_256<LIMBS>(x)
-                                 : residue_odd<LIMBS>(x, tab->pow26[t], tab->p[t], tab->inv_p[t]);
-          b |= (uint32_t)(uint8_t)(int8_t)r << (8 * i);
-        }
-        w[q] = b;
-      }
-      stage[sb][lane][wave * 2 + g] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
+    uint32_t w[4];
+    pack_residues<LIMBS, 16>(L, t, tab, w);
+    stage[sb][vl][g] = make_uint4(w[0], w[1], w[2], w[3]);
     __syncthreads();
-#pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-      const int row = pass * 32 + orow;
-      if (v0 + row < Vp)
-        *reinterpret_cast<uint4*>(R + (int64_t)t * plane + (v0 + row) * Kp + hb + ochunk * 16) =
-            stage[sb][row][ochunk];
-    }
+    *reinterpret_cast<uint4*>(out + (int64_t)t * plane) = stage[sb][orow][ochunk];
   }
 }
 
@@ -164,23 +145,37 @@ __global__ __launch_bounds__(256) void k2_split_strided(
 }
 
 // Contiguous vectors (columns of column-major B): entry h of vector v at
-// X[h + v ld].  One lane per (vector, group of 16 entries).
-template <typename T, int LIMBS>
+// X[h + v ld].  One lane per (vector, group of EPT consecutive entries):
+// neighbouring lanes read and write neighbouring groups, EPT-byte stores.
+constexpr int kK2EPT = 8;
+
+template <typename T, int LIMBS, int EPT = kK2EPT>
 __device__ __forceinline__ void k2_split_contig_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
     int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx) {
-  const int64_t groups = Kp / 16;
-  const int64_t g = bx * 256 + threadIdx.x;
-  if (g >= Vp * groups) return;
-  const int64_t v = g / groups;
-  const int64_t h0 = (g - v * groups) * 16;
+  const int64_t groups = Kp / EPT;
+  const int64_t gi = bx * 256 + threadIdx.x;
+  if (gi >= Vp * groups) return;
+  const int64_t v = gi / groups;
+  const int64_t h0 = (gi - v * groups) * EPT;
   const int32_t ev = v < nvec ? e[v] : 0;
-  double a[16];
-  const T* p = X + v * ld + h0;
+  Limbs<LIMBS> L[EPT];
+  {
+    double a[EPT];
+    const T* p = X + v * ld + h0;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) a[i] = (v < nvec && h0 + i < k) ? (double)p[i] : 0.0;
-  split16_store<LIMBS>(a, ev, tab, N, R + v * Kp + h0, Vp * Kp);
+    for (int i = 0; i < EPT; ++i) a[i] = (v < nvec && h0 + i < k) ? (double)p[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) L[i] = make_limbs<LIMBS>(a[i], ev);
+  }
+  int8_t* out = R + v * Kp + h0;
+  const int64_t plane = Vp * Kp;
+  for (int t = 0; t < N; ++t) {
+    uint32_t w[EPT / 4];
+    pack_residues<LIMBS, EPT>(L, t, tab, w);
+    store_packed<EPT>(out + (int64_t)t * plane, w);
+  }
 }
 
 template <typename T, int LIMBS>

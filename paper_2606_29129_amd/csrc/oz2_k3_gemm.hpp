@@ -43,13 +43,29 @@ __device__ __forceinline__ int swz_chunk(int row, int chunk) {
 }
 
 // Map a workgroup id to (plane, tile).  Workgroups are dispatched
-// round-robin over the 8 XCDs of MI355X, each with its own L2; the id is
-// first remapped so that every XCD receives one contiguous range of the
-// (plane, tile) sequence, and inside a plane tiles are walked in groups of
-// GM tile rows, column by column, so that neighbouring workgroups share
-// operand panels in L2.
+// round-robin over the 8 XCDs of MI355X (id mod 8), each XCD with its own L2,
+// all sharing the MALL (Infinity Cache).  When the tile grid allows it, ids
+// are taken in rounds of 256: in a round XCD x computes an 8 x 4 group of
+// tiles (32 tiles sharing 8 row panels of A and 4 column panels of B in its
+// L2), and the 8 groups of the round form one 32 x 8 block of tiles of the
+// same plane, so the XCDs fetch neighbouring panels at the same time and
+// share them through the MALL.  Rounds sweep a band of 32 tile rows column
+// block by column block, then the next band, then the next plane.  Other
+// grids fall back to giving each XCD one contiguous range of the
+// (plane, tile) sequence, walked in groups of 8 tile rows.
 __device__ __forceinline__ void tile_of(int id, int total, int tiles_m, int tiles_n,
                                         int* plane, int* tm, int* tn) {
+  constexpr int XM = 4, XN = 2;                 // groups per round: XM x XN
+  if (tiles_m % (8 * XM) == 0 && tiles_n % (4 * XN) == 0) {
+    const int x = id & 7, slot = id >> 3, r = slot >> 5, s = slot & 31;
+    const int rpp = tiles_m * tiles_n / 256;    // rounds per plane
+    const int rpb = tiles_n / (4 * XN);         // rounds per band
+    *plane = r / rpp;
+    const int rr = r - *plane * rpp, band = rr / rpb, c = rr - band * rpb;
+    *tm = band * 8 * XM + (x / XN) * 8 + (s & 7);
+    *tn = c * 4 * XN + (x % XN) * 4 + (s >> 3);
+    return;
+  }
   const int xcd = id & 7, slot = id >> 3;
   const int per = total >> 3, extra = total & 7;
   const int lin = (xcd < extra) ? xcd * (per + 1) + slot
@@ -80,35 +96,33 @@ __device__ __forceinline__ void wait_vmem_all() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #endif
 }
+__device__ __forceinline__ void wait_vmem_lds_all() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+#endif
+}
 
 // One BM x BN output tile of plane t (tile row tm, tile column tn).
 //
-// Main loop (one 128-byte k slab per iteration, two LDS buffers):
-//   wait for this wave's loads of slab kt, barrier (slab kt is in LDS for
-//   every wave, and the buffer of slab kt-1 is free), then for each of the
-//   four 32-byte k steps: read the next step's fragments, issue a quarter of
-//   slab kt+1's global->LDS loads, and run the TM x TN MFMAs, interleaved by
-//   scheduling groups so that memory instructions never queue up in front of
-//   the matrix core.  Lane l of wave w in load round i fills LDS slot
-//   16 (i 256 + 64 w + l); the slot's row and swizzled chunk decide which 16
-//   source bytes it fetches.
-// Scheduling groups for one MFMA k step: NL global loads, NM MFMAs and ND
-// LDS fragment reads interleaved as NL groups of
-// {DS read, MFMA, DS read, VMEM read, MFMA}.
-template <int NL, int NM, int ND>
-__device__ __forceinline__ void sched_k_step() {
-  static_assert(NM % (2 * NL) == 0 && ND % NL == 0, "group shape");
-#pragma unroll
-  for (int g = 0; g < NL; ++g) {
-    if constexpr (ND / NL / 2 > 0) __builtin_amdgcn_sched_group_barrier(0x100, ND / NL / 2, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, NM / NL / 2, 0);
-    if constexpr (ND / NL - ND / NL / 2 > 0)
-      __builtin_amdgcn_sched_group_barrier(0x100, ND / NL - ND / NL / 2, 0);
-    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, NM / NL / 2, 0);
-  }
-}
-
+// Main loop: one 128-byte k slab per iteration, two LDS buffers, four MFMA
+// k steps of 32 bytes per slab.  The instruction order is fixed explicitly
+// (a scheduling fence after every MFMA and the memory operations paired with
+// it), because with one wave per SIMD every stall of the in-order issue is a
+// bubble of the matrix core:
+//   * in k step kk, the TM + TN fragment reads of step kk + 1 follow the
+//     first TM + TN MFMAs, one after each;
+//   * the next slab's global->LDS loads are spread over k steps 0 and 1,
+//     evenly among their MFMAs (so they have two steps to land);
+//   * in the last k step, after a few MFMAs, the wave waits for its own
+//     loads and LDS reads and meets the others at the slab barrier; the
+//     next slab is then complete in LDS and the current buffer is free, and
+//     the next slab's step-0 fragment reads follow the remaining MFMAs.
+// So no k step waits for a fragment read issued less than a step earlier,
+// and the barrier sits among MFMAs instead of in front of them.  Lane l of
+// wave w in load round i fills LDS slot 16 (i 256 + 64 w + l); the slot's row
+// and swizzled chunk decide which 16 source bytes it fetches.  The next
+// slab's loads are issued unconditionally (the last slab re-fetches itself
+// into the idle buffer) so that the slab body is one basic block.
 template <int BM, int BN, int BK, int EPI>
 __device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
@@ -121,7 +135,6 @@ __device__ __forceinline__ void gemm_tile(
   constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
   constexpr int KS = BK / 32;                    // MFMA k steps per slab
   static_assert(A_LOADS * 256 == BM * CH && B_LOADS * 256 == BN * CH, "tile");
-  static_assert((A_LOADS + B_LOADS) % KS == 0, "loads per k step");
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -147,64 +160,68 @@ __device__ __forceinline__ void gemm_tile(
     const int s = i * 256 + tid, row = s / CH;
     offB[i] = (int64_t)row * Kp + swz_chunk<BK>(row, s % CH) * 16;
   }
-  // Loads of slab k0 into buffer buf, rounds with index = part (mod parts).
-  auto gload = [&](int buf, int64_t k0, int part, int parts) {
-#pragma unroll
-    for (int i = 0; i < A_LOADS; ++i)
-      if (i % parts == part) load_lds16(gA + offA[i] + k0, lds[buf] + (i * 256 + wave * 64) * 16);
-#pragma unroll
-    for (int i = 0; i < B_LOADS; ++i)
-      if ((A_LOADS + i) % parts == part)
-        load_lds16(gB + offB[i] + k0, lds[buf] + BM * BK + (i * 256 + wave * 64) * 16);
+  // Load round i (A rounds first, then B) of slab k0 into buffer buf.
+  auto gload1 = [&](int buf, int64_t k0, int i) {
+    if (i < A_LOADS)
+      load_lds16(gA + offA[i] + k0, lds[buf] + (i * 256 + wave * 64) * 16);
+    else
+      load_lds16(gB + offB[i - A_LOADS] + k0,
+                 lds[buf] + BM * BK + ((i - A_LOADS) * 256 + wave * 64) * 16);
   };
 
-  // Fragment reads for k step kk of LDS buffer buf into register set F.
+  // Fragment q (TM blocks of A, then TN blocks of B) of k step kk of LDS
+  // buffer buf into register set F.
   v4i fa[2][TM], fb[2][TN];
-  auto fload = [&](int buf, int kk, int F) {
-    const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
-    const int8_t* sB = lds[buf] + BM * BK + (wn * (BN / 2)) * BK;
+  auto fread1 = [&](int buf, int kk, int F, int q) {
     const int ch = kk * 2 + (lane >> 5);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      int row = i * 32 + (lane & 31);
-      fa[F][i] = *reinterpret_cast<const v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16);
-    }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      int row = j * 32 + (lane & 31);
-      fb[F][j] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
+    if (q < TM) {
+      const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
+      const int row = q * 32 + (lane & 31);
+      fa[F][q] = *reinterpret_cast<const v4i*>(sA + row * BK + swz_chunk<BK>(row, ch) * 16);
+    } else {
+      const int8_t* sB = lds[buf] + BM * BK + (wn * (BN / 2)) * BK;
+      const int row = (q - TM) * 32 + (lane & 31);
+      fb[F][q - TM] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
     }
   };
-  auto mfmas = [&](int F) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
-  };
+
+  constexpr int NM = TM * TN, NF = TM + TN, LOADS = A_LOADS + B_LOADS;
+  constexpr int LSTEPS = 2;                           // k steps carrying loads
+  constexpr int PER = (LOADS + LSTEPS - 1) / LSTEPS;  // loads per such step
+  constexpr int SP = NM / PER;                        // MFMAs per load
+  constexpr int BAR = (NM - NF) < 5 ? (NM - NF) : 5;  // MFMAs before the barrier
+  static_assert(KS % 2 == 0 && KS > LSTEPS && NM >= NF, "schedule shape");
+  static_assert(SP >= 1 && PER * LSTEPS >= LOADS, "loads fit the MFMA slots");
 
   const int nk = (int)(Kp / BK);
-  gload(0, 0, 0, 1);
+#pragma unroll
+  for (int i = 0; i < LOADS; ++i) gload1(0, 0, i);
+  wait_vmem_all();
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NF; ++q) fread1(0, 0, 0, q);
   int buf = 0;
   for (int kt = 0; kt < nk; ++kt) {
-    wait_vmem_all();
-    __syncthreads();
-    // The next slab's loads are issued unconditionally (the last iteration
-    // re-fetches the last slab into the idle buffer, which is never read) so
-    // that the whole slab is one basic block the scheduling groups can shape.
     const int64_t knext = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
-    fload(buf, 0, 0);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      if (kk + 1 < KS) fload(buf, kk + 1, (kk + 1) & 1);
-      gload(buf ^ 1, knext, kk, KS);
-      mfmas(kk & 1);
-      // Inside one k step: the TM x TN independent MFMAs with the next step's
-      // TM + TN fragment reads and the step's share of the global loads
-      // spread among them; nothing crosses into the neighbouring steps.
-      if (kk + 1 < KS) sched_k_step<(A_LOADS + B_LOADS) / KS, TM * TN, TM + TN>();
-      else             sched_k_step<(A_LOADS + B_LOADS) / KS, TM * TN, 0>();
-      __builtin_amdgcn_sched_barrier(0);
+      const int F = kk & 1;
+#pragma unroll
+      for (int idx = 0; idx < NM; ++idx) {
+        if (kk == KS - 1 && idx == BAR) {
+          wait_vmem_lds_all();
+          __syncthreads();
+        }
+        const int i = idx / TN, j = idx % TN;
+        acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
+        if (kk + 1 < KS && idx < NF) fread1(buf, kk + 1, F ^ 1, idx);
+        if (kk < LSTEPS && idx % SP == SP - 1) {
+          const int g = kk * PER + idx / SP;
+          if (g < LOADS) gload1(buf ^ 1, knext, g);
+        }
+        if (kk == KS - 1 && idx >= BAR && idx < BAR + NF) fread1(buf ^ 1, 0, 0, idx - BAR);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     buf ^= 1;
   }

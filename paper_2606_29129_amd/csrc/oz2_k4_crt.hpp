@@ -117,18 +117,21 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
 }
 
 // One wave per 32 x 32 block; lane l owns the 16 entries of the MFMA
-// accumulator layout (acc_row, acc_col).
+// accumulator layout (acc_row, acc_col).  The results go through a per-wave
+// LDS tile (column-major, columns padded to 33 entries) so that each store
+// instruction writes two whole 32-entry column segments of C.
 template <int S, typename TO>
 __device__ __forceinline__ void k4_crt_body(
     const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
     const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc, int64_t bx) {
-  const int lane = threadIdx.x & 63;
+  __shared__ TO tile[4][32][33];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t Mb = Mp / 32, Nb = Np / 32;
-  const int64_t blk = bx * 4 + (threadIdx.x >> 6);
+  const int64_t blk = bx * 4 + wave;
   const int64_t mb_used = (m + 31) / 32;
   const int64_t nb_used = (n + 31) / 32;
-  if (blk >= mb_used * nb_used) return;
+  if (blk >= mb_used * nb_used) return;  // whole wave: the tile is per wave
   const int64_t bi = blk % mb_used, bj = blk / mb_used;
   double acc[16][S];
 #pragma unroll
@@ -150,26 +153,41 @@ __device__ __forceinline__ void k4_crt_body(
       for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
     }
   }
-  const int64_t col = bj * 32 + acc_col(lane);
-  if (col >= n) return;
-  const int32_t f = eB[col];
+  const int lc = acc_col(lane);
+  const int64_t col = bj * 32 + lc;
+  const int32_t f = col < n ? eB[col] : 0;
   const ModTable& T = *tab;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int64_t row = bi * 32 + acc_row(r, lane);
-    if (row >= m) continue;
-    const int32_t e = eA[row];
-    double v;
-    if (e == kExpNonFinite || f == kExpNonFinite) {
-      v = __builtin_nan("");
-    } else {
-      double a[S];
+    const int lr = acc_row(r, lane);
+    const int64_t row = bi * 32 + lr;
+    double v = 0.0;
+    if (row < m && col < n) {
+      const int32_t e = eA[row];
+      if (e == kExpNonFinite || f == kExpNonFinite) {
+        v = __builtin_nan("");
+      } else {
+        double a[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) a[s] = acc[r][s];
-      if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
-      else v = crt_unscale<S, 24, -149>(a, T, e + f);
+        for (int s = 0; s < S; ++s) a[s] = acc[r][s];
+        if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
+        else v = crt_unscale<S, 24, -149>(a, T, e + f);
+      }
     }
-    C[row + col * ldc] = (TO)v;
+    tile[wave][lc][lr] = (TO)v;
+  }
+  // LDS operations of one wave complete in order; the fence keeps the
+  // compiler from moving the reads above the writes.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int orow = lane & 31;
+  const int64_t row = bi * 32 + orow;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int oc = 2 * i + (lane >> 5);
+    const int64_t c = bj * 32 + oc;
+    if (row < m && c < n) C[row + c * ldc] = tile[wave][oc][orow];
   }
 }
 

@@ -205,10 +205,10 @@ struct Debug {
 template <typename T, int LIMBS>
 void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, int64_t n,
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
-  dim3 gA((unsigned)(L.Mp / 64), (unsigned)(L.Kp / 128));
+  dim3 gA((unsigned)(L.Mp / kK2VB), (unsigned)(L.Kp / kK2HB));
   k2_split_strided<T, LIMBS><<<gA, 256, 0, g_stream>>>(
       A, lda, m, k, (const int32_t*)(ws + L.eA), tab, N, (int8_t*)(ws + L.RA), L.Mp, L.Kp);
-  int64_t work = L.Np * (L.Kp / 16);
+  int64_t work = L.Np * (L.Kp / kK2EPT);
   k2_split_contig<T, LIMBS><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
       B, ldb, n, k, (const int32_t*)(ws + L.eB), tab, N, (int8_t*)(ws + L.RB), L.Np, L.Kp);
 }
@@ -490,8 +490,8 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
           case kB_K1B: c = (q.n * L.nch + 255) / 256; break;
           case kB_FOLDA: c = (q.m + 255) / 256; break;
           case kB_FOLDB: c = (q.n + 255) / 256; break;
-          case kB_K2A: c = (L.Mp / 64) * (L.Kp / 128); break;
-          case kB_K2B: c = (L.Np * (L.Kp / 16) + 255) / 256; break;
+          case kB_K2A: c = (L.Mp / kK2VB) * (L.Kp / kK2HB); break;
+          case kB_K2B: c = (L.Np * (L.Kp / kK2EPT) + 255) / 256; break;
           default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
         }
         prefix[(size_t)st * (na + 1) + a] = acc;

@@ -1,0 +1,169 @@
+"""Summaries of rocprofv3 output for the committed profiles (host only).
+
+    python -m paper_2606_29129_amd.profiling stats DIR TITLE COMMAND > summary.md
+    python -m paper_2606_29129_amd.profiling traffic FETCH_DIR WRITE_DIR COMMAND \
+        --workload "m=16384 n=16384 k=16384 N=14" --copy-bytes B > traffic.txt
+
+``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
+--stats --output-format csv`` writes and prints a short markdown table of the
+library's kernels.  ``traffic`` reads the ``*counter_collection.csv`` of two
+``rocprofv3 --pmc`` runs (FETCH_SIZE, then WRITE_SIZE; both in KiB per
+dispatch), averages each counter over the dispatches of the INT8 GEMM kernel,
+and scales it by what the same counter reads for a plain streaming kernel of
+known size in the same run (``bench.py --traffic-calibration``: one
+``torch.abs`` over a float64 tensor of ``--copy-bytes`` bytes, which reads and
+writes that many bytes once).  The result is the file that ``bench.py`` reads
+to fill ``roofline.traffic``.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+K3_SOURCE = os.path.join(HERE, "csrc", "oz2_k3_gemm.hpp")
+K3_NAME = "k3_gemm_i8"
+COPY_NAME = "abs_kernel"
+
+
+def source_sha(path: str = K3_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> list[str]:
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return files
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").strip()
+
+
+def kernel_stats(d: str):
+    rows = []
+    for path in _find(d, "kernel_stats.csv"):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append(dict(name=r["Name"], calls=int(r["Calls"]),
+                                 total_ns=float(r["TotalDurationNs"]),
+                                 avg_ns=float(r["AverageNs"]),
+                                 pct=float(r["Percentage"]),
+                                 min_ns=float(r.get("MinNs", "nan") or "nan"),
+                                 max_ns=float(r.get("MaxNs", "nan") or "nan")))
+    return rows
+
+
+def stats_markdown(d: str, title: str, cmd: str) -> str:
+    rows = kernel_stats(d)
+    out = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
+           "```", cmd, "```", "",
+           "rocprofv3 kernel statistics (`*kernel_stats.csv`; durations in microseconds):", "",
+           "| kernel | calls | total us | average us | min us | max us | % of GPU time |",
+           "|---|---|---|---|---|---|---|"]
+    other = [0, 0.0, 0.0, 0]
+    for r in sorted(rows, key=lambda r: -r["total_ns"]):
+        s = _short(r["name"])
+        if s.startswith("oz2::"):
+            out.append(f"| `{s}` | {r['calls']} | {r['total_ns'] / 1e3:.1f} | "
+                       f"{r['avg_ns'] / 1e3:.1f} | {r['min_ns'] / 1e3:.1f} | "
+                       f"{r['max_ns'] / 1e3:.1f} | {r['pct']:.2f} |")
+        else:
+            other[0] += r["calls"]
+            other[1] += r["total_ns"]
+            other[2] += r["pct"]
+            other[3] += 1
+    out.append(f"| (other kernels: input generation, copies; {other[3]} kinds) | {other[0]} | "
+               f"{other[1] / 1e3:.1f} | - | - | - | {other[2]:.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def counter_means(d: str, counter: str):
+    """{short kernel name: mean over dispatches of the counter's per-dispatch
+    total} and the dispatch counts."""
+    per = defaultdict(float)
+    names = {}
+    for path in _find(d, "counter_collection.csv"):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                key = (path, r["Dispatch_Id"])
+                per[key] += float(r["Counter_Value"])
+                names[key] = _short(r["Kernel_Name"])
+    sums, counts = defaultdict(float), defaultdict(int)
+    for key, v in per.items():
+        sums[names[key]] += v
+        counts[names[key]] += 1
+    return {k: sums[k] / counts[k] for k in sums}, dict(counts)
+
+
+def _pick(means: dict, needle: str) -> str:
+    hits = [k for k in means if needle in k]
+    if len(hits) != 1:
+        raise ValueError(f"expected one kernel matching {needle!r}, found {hits}")
+    return hits[0]
+
+
+def traffic_text(fetch_dir: str, write_dir: str, cmd: str, workload: str, copy_bytes: int) -> str:
+    fm, fc = counter_means(fetch_dir, "FETCH_SIZE")
+    wm, wc = counter_means(write_dir, "WRITE_SIZE")
+    k3f, k3w = _pick(fm, K3_NAME), _pick(wm, K3_NAME)
+    cpf, cpw = _pick(fm, COPY_NAME), _pick(wm, COPY_NAME)
+    f_scale = copy_bytes / (fm[cpf] * 1024.0)
+    w_scale = copy_bytes / (wm[cpw] * 1024.0)
+    fetch_b = fm[k3f] * 1024.0 * f_scale
+    write_b = wm[k3w] * 1024.0 * w_scale
+    lines = [
+        "# HBM traffic of the INT8 GEMM kernel (rocprofv3 --pmc, two passes)",
+        f"command: {cmd}",
+        f"kernel: {k3f}",
+        f"kernel_source_sha256: {source_sha()}",
+        f"workload: {workload}",
+        f"k3_dispatches_fetch_pass: {fc[k3f]}",
+        f"k3_dispatches_write_pass: {wc[k3w]}",
+        f"k3_fetch_size_kib_per_dispatch: {fm[k3f]:.1f}",
+        f"k3_write_size_kib_per_dispatch: {wm[k3w]:.1f}",
+        f"copy_kernel: {cpf}",
+        f"copy_bytes_read_and_written: {copy_bytes}",
+        f"copy_fetch_size_kib: {fm[cpf]:.1f}",
+        f"copy_write_size_kib: {wm[cpw]:.1f}",
+        f"fetch_scale: {f_scale:.4f}",
+        f"write_scale: {w_scale:.4f}",
+        f"hbm_fetch_bytes_per_launch: {fetch_b:.6e}",
+        f"hbm_write_bytes_per_launch: {write_b:.6e}",
+        f"hbm_bytes_per_launch: {fetch_b + write_b:.6e}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("title")
+    s.add_argument("command")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("command")
+    t.add_argument("--workload", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        sys.stdout.write(stats_markdown(a.dir, a.title, a.command))
+    else:
+        sys.stdout.write(traffic_text(a.fetch_dir, a.write_dir, a.command, a.workload,
+                                      a.copy_bytes))
+
+
+if __name__ == "__main__":
+    main()

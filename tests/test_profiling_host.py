@@ -1,0 +1,62 @@
+"""Host-side checks of the rocprofv3 summarisers (synthetic CSV files)."""
+import csv
+
+import pytest
+
+from paper_2606_29129_amd import profiling
+
+
+def _write(path, header, rows):
+    path.parent.mkdir(parents=True, exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+K3 = "void oz2::k3_gemm_i8<256, 256, 128, 0>(signed char const*, ...)"
+COPY = ("void at::native::vectorized_elementwise_kernel<4, at::native::abs_kernel_cuda"
+        "(at::TensorIteratorBase&)::{lambda()#1}>(int, ...)")
+HDR = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def test_traffic_scaling(tmp_path):
+    # two K3 dispatches (one split over two rows), one copy of 1 MiB read as 2 MiB
+    _write(tmp_path / "f" / "host" / "1_counter_collection.csv", HDR, [
+        [1, COPY, "FETCH_SIZE", 2048.0],
+        [2, K3, "FETCH_SIZE", 1000.0], [2, K3, "FETCH_SIZE", 1000.0],
+        [3, K3, "FETCH_SIZE", 4000.0],
+    ])
+    _write(tmp_path / "w" / "host" / "1_counter_collection.csv", HDR, [
+        [1, COPY, "WRITE_SIZE", 1024.0], [2, K3, "WRITE_SIZE", 10.0],
+    ])
+    txt = profiling.traffic_text(str(tmp_path / "f"), str(tmp_path / "w"), "cmd",
+                                 "m=1 n=1 k=1 N=2", 1 << 20)
+    kv = dict(l.split(": ", 1) for l in txt.splitlines() if ": " in l)
+    assert kv["k3_dispatches_fetch_pass"] == "2"
+    assert float(kv["fetch_scale"]) == pytest.approx(0.5)
+    assert float(kv["write_scale"]) == pytest.approx(1.0)
+    # mean fetch 3000 KiB scaled by 0.5, write 10 KiB
+    assert float(kv["hbm_bytes_per_launch"]) == pytest.approx(1500 * 1024 + 10 * 1024)
+    assert kv["kernel_source_sha256"] == profiling.source_sha()
+
+
+def test_stats_markdown(tmp_path):
+    _write(tmp_path / "s" / "x_kernel_stats.csv",
+           ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs"],
+           [[K3, 2, 2e6, 1e6, 90.0, 0.9e6, 1.1e6], [COPY, 1, 1e5, 1e5, 10.0, 1e5, 1e5]])
+    md = profiling.stats_markdown(str(tmp_path / "s"), "t", "cmd")
+    assert "| `oz2::k3_gemm_i8<256, 256, 128, 0>` | 2 | 2000.0 | 1000.0 | 900.0 | 1100.0 | 90.00 |" in md
+    assert "other kernels" in md
+
+
+def test_bench_reads_traffic_file(tmp_path, monkeypatch):
+    import bench
+    f = tmp_path / "t.txt"
+    f.write_text(f"kernel_source_sha256: {profiling.source_sha()}\n"
+                 "workload: m=4 n=4 k=4 N=3\nhbm_bytes_per_launch: 1.5e9\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.load_traffic(4, 4, 4, 3) == 1.5e9
+    assert bench.load_traffic(4, 4, 4, 4) is None
+    f.write_text("kernel_source_sha256: 0\nworkload: m=4 n=4 k=4 N=3\nhbm_bytes_per_launch: 1\n")
+    assert bench.load_traffic(4, 4, 4, 3) is None
