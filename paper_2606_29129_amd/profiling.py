@@ -28,7 +28,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 K3_SOURCE = os.path.join(HERE, "csrc", "oz2_k3_gemm.hpp")
 K3_NAME = "k3_gemm_i8"
-COPY_NAME = "abs_kernel"
+COPY_NAME = "AbsFunctor"
 
 
 def source_sha(path: str = K3_SOURCE) -> str:

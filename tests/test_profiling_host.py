@@ -15,8 +15,8 @@ def _write(path, header, rows):
 
 
 K3 = "void oz2::k3_gemm_i8<256, 256, 128, 0>(signed char const*, ...)"
-COPY = ("void at::native::vectorized_elementwise_kernel<4, at::native::abs_kernel_cuda"
-        "(at::TensorIteratorBase&)::{lambda()#1}>(int, ...)")
+COPY = ("void at::native::vectorized_elementwise_kernel<4, at::native::AbsFunctor<double>, "
+        "std::array<char*, 2ul> >(int, at::native::AbsFunctor<double>, std::array<char*, 2ul>)")
 HDR = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
 
 
