@@ -117,8 +117,12 @@ __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ pro
     if (i >= nitems) break;
     const WorkItem w = items[i];
     const BatchProb& P = probs[w.p];
-    gemm_tile<kBatchTile, kBatchTile, 128, 0>(P.RA, P.RB, P.U, nullptr, nullptr, P.m, P.n, P.Mp,
-                                             P.Np, P.Kp, P.tab, w.t, w.tm, w.tn, lds);
+    // A 128 x 128 tile has only 4 MFMAs per k step per wave, and two
+    // workgroups share a CU: the slab-top barrier with the next slab's loads
+    // spread over three k steps measured best for it.
+    gemm_tile<kBatchTile, kBatchTile, 128, 0, false, 3>(P.RA, P.RB, P.U, nullptr, nullptr, P.m,
+                                                        P.n, P.Mp, P.Np, P.Kp, P.tab, w.t, w.tm,
+                                                        w.tn, lds);
   }
 }
 

@@ -22,6 +22,8 @@
 // integer atomicMax (entries are >= 0, and the maxima start at 0).
 #pragma once
 
+#include <type_traits>
+
 #include "oz2_math.hpp"
 #include "oz2_tables.hpp"
 
@@ -120,10 +122,10 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 // So no k step waits for a fragment read issued less than a step earlier,
 // and the barrier sits among MFMAs instead of in front of them.  Lane l of
 // wave w in load round i fills LDS slot 16 (i 256 + 64 w + l); the slot's row
-// and swizzled chunk decide which 16 source bytes it fetches.  The next
-// slab's loads are issued unconditionally (the last slab re-fetches itself
-// into the idle buffer) so that the slab body is one basic block.
-template <int BM, int BN, int BK, int EPI>
+// and swizzled chunk decide which 16 source bytes it fetches.  The last slab
+// is a separate copy of the body without loads, barrier or read-ahead, so
+// that every slab body is one basic block without conditional loads.
+template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = true, int LSTEPS = 2>
 __device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
@@ -186,45 +188,61 @@ __device__ __forceinline__ void gemm_tile(
   };
 
   constexpr int NM = TM * TN, NF = TM + TN, LOADS = A_LOADS + B_LOADS;
-  constexpr int LSTEPS = 2;                           // k steps carrying loads
-  constexpr int PER = (LOADS + LSTEPS - 1) / LSTEPS;  // loads per such step
+  constexpr int PER = (LOADS + LSTEPS - 1) / LSTEPS;  // loads per loading step
   constexpr int SP = NM / PER;                        // MFMAs per load
   constexpr int BAR = (NM - NF) < 5 ? (NM - NF) : 5;  // MFMAs before the barrier
-  static_assert(KS % 2 == 0 && KS > LSTEPS && NM >= NF, "schedule shape");
+  static_assert(KS % 2 == 0 && NM >= NF, "schedule shape");
+  static_assert(LSTEPS <= (EARLY_BARRIER ? KS - 1 : KS), "loads land before the barrier");
   static_assert(SP >= 1 && PER * LSTEPS >= LOADS, "loads fit the MFMA slots");
 
   const int nk = (int)(Kp / BK);
 #pragma unroll
   for (int i = 0; i < LOADS; ++i) gload1(0, 0, i);
-  wait_vmem_all();
-  __syncthreads();
+  if constexpr (EARLY_BARRIER) {
+    wait_vmem_all();
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NF; ++q) fread1(0, 0, 0, q);
+    for (int q = 0; q < NF; ++q) fread1(0, 0, 0, q);
+  }
+  // One slab; MORE = false for the last one, which has no next slab to load
+  // or to read ahead (a separate copy, so that both stay one basic block).
   int buf = 0;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int64_t knext = (int64_t)(kt + 1 < nk ? kt + 1 : kt) * BK;
+  auto slab = [&](int kt, auto more_tag) {
+    constexpr bool MORE = decltype(more_tag)::value;
+    const int64_t knext = (int64_t)(kt + 1) * BK;
+    if constexpr (!EARLY_BARRIER) {
+      // Barrier at the top of the slab: slab kt is in LDS and every wave is
+      // done with the buffer the next loads overwrite.
+      wait_vmem_lds_all();
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NF; ++q) fread1(buf, 0, 0, q);
+    }
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const int F = kk & 1;
 #pragma unroll
       for (int idx = 0; idx < NM; ++idx) {
-        if (kk == KS - 1 && idx == BAR) {
+        if (MORE && EARLY_BARRIER && kk == KS - 1 && idx == BAR) {
           wait_vmem_lds_all();
           __syncthreads();
         }
         const int i = idx / TN, j = idx % TN;
         acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
         if (kk + 1 < KS && idx < NF) fread1(buf, kk + 1, F ^ 1, idx);
-        if (kk < LSTEPS && idx % SP == SP - 1) {
+        if (MORE && kk < LSTEPS && idx % SP == SP - 1) {
           const int g = kk * PER + idx / SP;
           if (g < LOADS) gload1(buf ^ 1, knext, g);
         }
-        if (kk == KS - 1 && idx >= BAR && idx < BAR + NF) fread1(buf ^ 1, 0, 0, idx - BAR);
+        if (MORE && EARLY_BARRIER && kk == KS - 1 && idx >= BAR && idx < BAR + NF)
+          fread1(buf ^ 1, 0, 0, idx - BAR);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
     buf ^= 1;
-  }
+  };
+  for (int kt = 0; kt + 1 < nk; ++kt) slab(kt, std::true_type{});
+  slab(nk - 1, std::false_type{});
   wait_vmem_all();  // no load may still target LDS when the tile returns
 
   const int64_t Mb = Mp / 32;
