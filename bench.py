@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--N", type=int, default=14)
     ap.add_argument("--phi", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="revised", choices=["revised", "original"])
+    ap.add_argument("--mode", default="revised", choices=["revised", "original", "accurate"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
@@ -203,7 +203,11 @@ def main():
     m = args.m or args.size
     n = args.n or args.size
     k = args.k or args.size
-    N, mode = args.N, (0 if args.mode == "revised" else 1)
+    N, mode = args.N, {"revised": 0, "original": 1, "accurate": 2}[args.mode]
+    if mode == 2 and not args.no_cpu_baseline:
+        # the oracle's accurate-mode exponents need the whole bar product
+        _log("accurate mode: no sampled CPU oracle leg")
+        args.no_cpu_baseline = True
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 

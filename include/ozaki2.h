@@ -150,13 +150,29 @@ int ozaki2_query_constants(int N, int32_t* moduli, float* p_prime_prop,
  * synchronises the stream and writes into ms[OZ2_NUM_STAGES] the summed
  * milliseconds per stage since timing was enabled (or last read), and into
  * *calls the number of calls timed, then resets the sums.
- * Stages: 0 norms and exponents (K1), 1 convert and split (K2),
- * 2 INT8 GEMMs (K3), 3 CRT and unscale (K4), 4 other (accurate-mode
- * scale GEMM, zero fill).
+ * Stages: 0 norms and exponents (K1; in accurate mode also the bar matrices
+ * and their INT8 GEMM), 1 convert and split (K2), 2 INT8 GEMMs (K3), 3 CRT
+ * and unscale (K4), 4 other (zero fill, bookkeeping).
  */
 #define OZ2_NUM_STAGES 5
 int ozaki2_set_timing(int enable);
 int ozaki2_get_stage_times(double* ms, int* calls);
+
+/*
+ * GEMM tile of ozaki2_dgemm / ozaki2_sgemm (Step 3's N INT8 products; the
+ * batched path always uses 128 x 128).  OZ2_TILE_AUTO (the default) picks per
+ * call from m, n, k and N with a cost model of padded work and workgroup
+ * rounds; the others force one shape (rows x columns of C per workgroup).
+ * Results do not depend on the tile.  ozaki2_set_tile returns 0, or -1 for
+ * an unknown value; ozaki2_get_tile writes the tile a call with these sizes
+ * would use and returns 0, or minus the index of a bad argument.
+ */
+#define OZ2_TILE_AUTO    0
+#define OZ2_TILE_256x256 1
+#define OZ2_TILE_128x128 2
+#define OZ2_TILE_256x64  3
+int ozaki2_set_tile(int tile);
+int ozaki2_get_tile(int64_t m, int64_t n, int64_t k, int N, int* tile);
 
 /*
  * Batched emulated DGEMM.  One problem of a batch, column-major as for

@@ -1,4 +1,4 @@
-"""Autotuner: the number of moduli N per accuracy target.
+"""Autotuner: the number of moduli N per accuracy target, and the GEMM tile.
 
 The error of the emulated product is set by how many bits of each entry the
 scaled integers keep (Section 2.2: more moduli, larger P, wider integers) and
@@ -16,6 +16,14 @@ paper's experiments, (rand - 0.5) exp(phi randn), is controlled by phi
 
 The exact reference is computed here with Python integers (every binary64
 value is an integer times a power of two).
+
+Tiles: the library chooses among three GEMM tiles (256x256, 128x128,
+256x64; ``ozaki2_set_tile``) with a cost model of padded work and workgroup
+rounds whose constants (a relative rate and a fixed per-round cost in k
+slabs for each tile) come from ``measure_tiles`` (times of ``ozaki2_dgemm``
+with each tile forced, over a grid of shapes and N, stored in
+``autotune_tiles.json``) and ``fit_tile_model`` (the constants that minimise
+the summed slowdown of the model's pick against the best measured tile).
 """
 from __future__ import annotations
 
@@ -27,6 +35,12 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "autotune_table.json")
+TILE_TABLE = os.path.join(HERE, "autotune_tiles.json")
+TILES = {1: (256, 256), 2: (128, 128), 3: (256, 64)}     # OZ2_TILE_* -> (rows, cols)
+TILE_SHAPES = ((1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192, 8192, 8192),
+               (8192, 8192, 1024), (4096, 4096, 512), (2048, 2048, 8192), (65536, 64, 4096),
+               (32768, 128, 4096), (16384, 256, 2048), (512, 512, 4096), (3000, 3000, 3000),
+               (16384, 16384, 16384))
 
 K_GRID = (64, 256, 1024, 2048)
 PHI_GRID = (0.5, 1.0, 1.5, 2.0, 2.5, 3.0)
@@ -134,5 +148,108 @@ def calibrate(m: int = 256, block: int = 32, seed: int = 7, path: str = TABLE, l
     return table
 
 
+def measure_tiles(shapes=TILE_SHAPES, Ns=(14, 20), phi=1.0, path: str = TILE_TABLE, log=print):
+    """Time ozaki2_dgemm with each tile forced (median-free mean of a few
+    calls after two warmups) and store the table.  Needs a GPU."""
+    import torch
+    from . import inputs
+    from . import ozaki2 as oz
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for (m, n, k) in shapes:
+        A = inputs.ozaki_matrix_torch(m, k, phi, 0, 0, dev)
+        B = inputs.ozaki_matrix_torch(k, n, phi, 0, 1, dev)
+        Acm, Bcm = A.t().contiguous(), B.t().contiguous()
+        C = torch.empty((n, m), dtype=torch.float64, device=dev)
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        rec = dict(m=m, n=n, k=k, ms={})
+        for N in Ns:
+            for tile in TILES:
+                oz._check("ozaki2_set_tile", oz.ozaki2_set_tile(tile))
+                f = lambda: oz._check("ozaki2_dgemm", oz.ozaki2_dgemm(
+                    m, n, k, Acm, m, Bcm, k, C, m, N, 0))
+                f()
+                f()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                reps = 5 if m * n * k < 2 ** 36 else 2
+                e0.record()
+                for _ in range(reps):
+                    f()
+                e1.record()
+                torch.cuda.synchronize()
+                rec["ms"][f"{N}/{tile}"] = round(e0.elapsed_time(e1) / reps, 4)
+        oz.ozaki2_set_tile(0)
+        rows.append(rec)
+        log(json.dumps(rec))
+        del A, B, Acm, Bcm, C
+        torch.cuda.empty_cache()
+    table = dict(phi=phi, Ns=list(Ns), tiles={str(t): list(v) for t, v in TILES.items()},
+                 shapes=rows)
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    return table
+
+
+def tile_model_time(m, n, k, N, tile, rate, fixed, per_cu=(0, 1, 2, 2)):
+    """The library's cost model (relative units) for one tile."""
+    bm, bn = TILES[tile]
+    tiles = math.ceil(m / bm) * math.ceil(n / bn) * N
+    rounds = math.ceil(tiles / (256 * per_cu[tile]))
+    return rounds * bm * bn * per_cu[tile] * (math.ceil(k / 128) + fixed[tile]) / rate[tile]
+
+
+def tile_regret(table, rate, fixed):
+    """(summed, worst) relative slowdown of the model's pick vs the best
+    measured tile over the table."""
+    total = worst = 0.0
+    for rec in table["shapes"]:
+        for N in table["Ns"]:
+            ms = {t: rec["ms"][f"{N}/{t}"] for t in TILES}
+            pick = min(TILES, key=lambda t: tile_model_time(rec["m"], rec["n"], rec["k"], N, t,
+                                                            rate, fixed))
+            r = ms[pick] / min(ms.values()) - 1.0
+            total += r
+            worst = max(worst, r)
+    return total, worst
+
+
+def fit_tile_model(table=None, path: str = TILE_TABLE):
+    """Grid search of the rates of the two smaller tiles and the fixed
+    per-round costs; among the fits within 0.3% of the least summed slowdown,
+    the one whose rates are closest to the large-problem rates measured in
+    the table (16384^3) is returned as (rate, fixed, summed, worst)."""
+    if table is None:
+        with open(path) as f:
+            table = json.load(f)
+    big = [r for r in table["shapes"] if r["m"] == r["n"] == r["k"] == 16384]
+    ref = {2: 0.8, 3: 0.45}
+    if big:
+        N = table["Ns"][0]
+        for t in (2, 3):
+            ref[t] = big[0]["ms"][f"{N}/1"] / big[0]["ms"][f"{N}/{t}"]
+    fits = []
+    for r2 in [x / 100 for x in range(45, 90, 5)]:
+        for r3 in [x / 100 for x in range(25, 70, 5)]:
+            for f1 in (0, 2, 4, 6, 8, 12, 16):
+                for f2 in (0, 1, 2, 4):
+                    for f3 in (0, 1, 2, 4):
+                        rate = {1: 1.0, 2: r2, 3: r3}
+                        fixed = {1: f1, 2: f2, 3: f3}
+                        tot, worst = tile_regret(table, rate, fixed)
+                        fits.append((tot, worst, rate, fixed))
+    best = min(f[0] for f in fits)
+    near = [f for f in fits if f[0] <= best + 0.003]
+    near.sort(key=lambda f: abs(f[2][2] - ref[2]) + abs(f[2][3] - ref[3]) + 0.001 * f[3][1])
+    tot, worst, rate, fixed = near[0]
+    return rate, fixed, tot, worst
+
+
 if __name__ == "__main__":
-    calibrate(log=lambda s: print(s, flush=True))
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "tiles":
+        measure_tiles(log=lambda s: print(s, flush=True))
+        print(fit_tile_model())
+    else:
+        calibrate(log=lambda s: print(s, flush=True))

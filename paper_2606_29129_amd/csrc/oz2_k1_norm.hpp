@@ -113,17 +113,44 @@ __global__ __launch_bounds__(256) void k1_partials_contig(
 // mode 0: Algorithm 2 (revised); mode 1: Algorithm 1 (original fast mode).
 // A squared norm that is NaN or +inf yields the sentinel exponent and sets
 // bit OZ2_STATUS_NONFINITE in *status.
+// Fold the chunk sums of vector v left to right with rounded-up additions
+// (and their maxima): 16 loads are issued ahead of each 16 sequential adds
+// so that the chain waits on arithmetic, not on memory latency.
+__device__ __forceinline__ void fold_chunks(const double* __restrict__ part,
+                                            const double* __restrict__ pmax, int64_t nchunks,
+                                            int64_t nvec, int64_t v, double* S_out, double* mx_out) {
+  double S = 0.0, mx = 0.0;
+  int64_t c = 0;
+  for (; c + 16 <= nchunks; c += 16) {
+    double b[16], q[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) b[i] = part[(c + i) * nvec + v];
+    if (pmax) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) q[i] = pmax[(c + i) * nvec + v];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      S = ru_add(S, b[i]);
+      if (pmax) mx = fmax(mx, q[i]);
+    }
+  }
+  for (; c < nchunks; ++c) {
+    S = ru_add(S, part[c * nvec + v]);
+    if (pmax) mx = fmax(mx, pmax[c * nvec + v]);
+  }
+  *S_out = S;
+  *mx_out = mx;
+}
+
 __device__ __forceinline__ void k1_fold_body(
     const double* __restrict__ part, const double* __restrict__ pmax, int64_t nchunks,
     int64_t nvec, int mode, const ModTable* __restrict__ tab, int32_t* __restrict__ e_out,
     double* __restrict__ S_out, int* __restrict__ status, int64_t bx) {
   const int64_t v = bx * 256 + threadIdx.x;
   if (v >= nvec) return;
-  double S = 0.0, mx = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) {
-    S = ru_add(S, part[c * nvec + v]);
-    if (pmax) mx = fmax(mx, pmax[c * nvec + v]);
-  }
+  double S, mx;
+  fold_chunks(part, pmax, nchunks, nvec, v, &S, &mx);
   if (S_out) S_out[v] = S;
   int32_t e;
   if (!(S <= 1.7976931348623157e308)) {
@@ -154,11 +181,8 @@ __global__ __launch_bounds__(256) void k1_fold_first(
     int64_t nvec, int32_t* __restrict__ e1_out, int* __restrict__ status) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (v >= nvec) return;
-  double S = 0.0, mx = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) {
-    S = ru_add(S, part[c * nvec + v]);
-    mx = fmax(mx, pmax[c * nvec + v]);
-  }
+  double S, mx;
+  fold_chunks(part, pmax, nchunks, nvec, v, &S, &mx);
   int32_t e;
   if (!(S <= 1.7976931348623157e308)) {
     e = kExpNonFinite;

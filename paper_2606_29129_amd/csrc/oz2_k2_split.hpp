@@ -195,56 +195,62 @@ OZ2_HD int8_t bar_value(double a, int32_t e) {
   return (int8_t)(v == v ? v : 0.0);
 }
 
-template <typename T>
+// Bar plane of the strided operand: the geometry of k2_split_strided (VB
+// vectors x (256 / VB) 16 entries per block, one LDS staging pass).
+template <typename T, int VB = kK2VB>
 __global__ __launch_bounds__(256) void k2_bar_strided(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= Vp) return;
+  constexpr int G = 256 / VB, HB = G * 16;
+  __shared__ uint4 stage[VB][G + 1];
+  const int vl = threadIdx.x % VB, g = threadIdx.x / VB;
+  const int64_t v0 = (int64_t)blockIdx.x * VB, v = v0 + vl;
+  const int64_t h0 = (int64_t)blockIdx.y * HB + g * 16;
   const int32_t ev = v < nvec ? e[v] : kExpZero;
-  const int64_t hb = (int64_t)blockIdx.y * 128;
-#pragma unroll 1
-  for (int g = 0; g < 8; ++g) {
-    const int64_t h0 = hb + g * 16;
-    uint32_t w[4];
+  double a[16];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t b = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t h = h0 + 4 * q + i;
-        double a = (v < nvec && h < k) ? (double)X[v + h * ld] : 0.0;
-        b |= (uint32_t)(uint8_t)bar_value(a, ev) << (8 * i);
-      }
-      w[q] = b;
-    }
-    *reinterpret_cast<uint4*>(R + v * Kp + h0) = make_uint4(w[0], w[1], w[2], w[3]);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k2_bar_contig(
-    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
-    const int32_t* __restrict__ e, int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
-  const int64_t groups = Kp / 16;
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= Vp * groups) return;
-  const int64_t v = g / groups;
-  const int64_t h0 = (g - v * groups) * 16;
-  const int32_t ev = v < nvec ? e[v] : kExpZero;
+  for (int i = 0; i < 16; ++i)
+    a[i] = (v < nvec && h0 + i < k) ? (double)X[v + (h0 + i) * ld] : 0.0;
   uint32_t w[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     uint32_t b = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t h = h0 + 4 * q + i;
-      double a = (v < nvec && h < k) ? (double)X[v * ld + h] : 0.0;
-      b |= (uint32_t)(uint8_t)bar_value(a, ev) << (8 * i);
-    }
+    for (int i = 0; i < 4; ++i) b |= (uint32_t)(uint8_t)bar_value(a[4 * q + i], ev) << (8 * i);
     w[q] = b;
   }
-  *reinterpret_cast<uint4*>(R + v * Kp + h0) = make_uint4(w[0], w[1], w[2], w[3]);
+  stage[vl][g] = make_uint4(w[0], w[1], w[2], w[3]);
+  __syncthreads();
+  const int orow = threadIdx.x / G, ochunk = threadIdx.x % G;
+  *reinterpret_cast<uint4*>(R + (v0 + orow) * Kp + (int64_t)blockIdx.y * HB + ochunk * 16) =
+      stage[orow][ochunk];
+}
+
+// Bar plane of the contiguous operand: one lane per kK2EPT consecutive
+// entries, as k2_split_contig.
+template <typename T, int EPT = kK2EPT>
+__global__ __launch_bounds__(256) void k2_bar_contig(
+    const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
+    const int32_t* __restrict__ e, int8_t* __restrict__ R, int64_t Vp, int64_t Kp) {
+  const int64_t groups = Kp / EPT;
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gi >= Vp * groups) return;
+  const int64_t v = gi / groups;
+  const int64_t h0 = (gi - v * groups) * EPT;
+  const int32_t ev = v < nvec ? e[v] : kExpZero;
+  double a[EPT];
+  const T* p = X + v * ld + h0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) a[i] = (v < nvec && h0 + i < k) ? (double)p[i] : 0.0;
+  uint32_t w[EPT / 4];
+#pragma unroll
+  for (int q = 0; q < EPT / 4; ++q) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b |= (uint32_t)(uint8_t)bar_value(a[4 * q + i], ev) << (8 * i);
+    w[q] = b;
+  }
+  store_packed<EPT>(R + v * Kp + h0, w);
 }
 
 }  // namespace oz2

@@ -49,25 +49,33 @@ __device__ __forceinline__ int swz_chunk(int row, int chunk) {
 // all sharing the MALL (Infinity Cache).  When the tile grid allows it, ids
 // are taken in rounds of 256: in a round XCD x computes an 8 x 4 group of
 // tiles (32 tiles sharing 8 row panels of A and 4 column panels of B in its
-// L2), and the 8 groups of the round form one 32 x 8 block of tiles of the
-// same plane, so the XCDs fetch neighbouring panels at the same time and
-// share them through the MALL.  Rounds sweep a band of 32 tile rows column
-// block by column block, then the next band, then the next plane.  Other
-// grids fall back to giving each XCD one contiguous range of the
-// (plane, tile) sequence, walked in groups of 8 tile rows.
+// L2), and the 8 groups of the round form one (8 XM) x (4 XN) block of tiles
+// of the same plane (XM XN = 8; 32 x 8 preferred, else 16 x 16, else
+// 8 x 32), so the XCDs fetch neighbouring panels at the same time and share
+// them through the MALL.  Rounds sweep a band of 8 XM tile rows column block
+// by column block, then the next band, then the next plane.  Other grids
+// fall back to giving each XCD one contiguous range of the (plane, tile)
+// sequence, walked in groups of 8 tile rows.
+template <int XM>
+__device__ __forceinline__ bool tile_of_rounds(int id, int tiles_m, int tiles_n, int* plane,
+                                               int* tm, int* tn) {
+  constexpr int XN = 8 / XM;
+  if (tiles_m % (8 * XM) != 0 || tiles_n % (4 * XN) != 0) return false;
+  const int x = id & 7, slot = id >> 3, r = slot >> 5, s = slot & 31;
+  const int rpp = tiles_m * tiles_n / 256;    // rounds per plane
+  const int rpb = tiles_n / (4 * XN);         // rounds per band
+  *plane = r / rpp;
+  const int rr = r - *plane * rpp, band = rr / rpb, c = rr - band * rpb;
+  *tm = band * 8 * XM + (x / XN) * 8 + (s & 7);
+  *tn = c * 4 * XN + (x % XN) * 4 + (s >> 3);
+  return true;
+}
+
 __device__ __forceinline__ void tile_of(int id, int total, int tiles_m, int tiles_n,
                                         int* plane, int* tm, int* tn) {
-  constexpr int XM = 4, XN = 2;                 // groups per round: XM x XN
-  if (tiles_m % (8 * XM) == 0 && tiles_n % (4 * XN) == 0) {
-    const int x = id & 7, slot = id >> 3, r = slot >> 5, s = slot & 31;
-    const int rpp = tiles_m * tiles_n / 256;    // rounds per plane
-    const int rpb = tiles_n / (4 * XN);         // rounds per band
-    *plane = r / rpp;
-    const int rr = r - *plane * rpp, band = rr / rpb, c = rr - band * rpb;
-    *tm = band * 8 * XM + (x / XN) * 8 + (s & 7);
-    *tn = c * 4 * XN + (x % XN) * 4 + (s >> 3);
-    return;
-  }
+  if (tile_of_rounds<4>(id, tiles_m, tiles_n, plane, tm, tn)) return;
+  if (tile_of_rounds<2>(id, tiles_m, tiles_n, plane, tm, tn)) return;
+  if (tile_of_rounds<1>(id, tiles_m, tiles_n, plane, tm, tn)) return;
   const int xcd = id & 7, slot = id >> 3;
   const int per = total >> 3, extra = total & 7;
   const int lin = (xcd < extra) ? xcd * (per + 1) + slot
@@ -125,7 +133,12 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 // and swizzled chunk decide which 16 source bytes it fetches.  The last slab
 // is a separate copy of the body without loads, barrier or read-ahead, so
 // that every slab body is one basic block without conditional loads.
-template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = true, int LSTEPS = 2>
+// EARLY_BARRIER (the default for 256 x 256 tiles) places the slab barrier
+// inside the last k step as described above; smaller tiles, with fewer MFMAs
+// per k step and two workgroups per CU, keep the barrier at the top of the
+// slab and spread the loads over three k steps (measured best for them).
+template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = (BM >= 256 && BN >= 256),
+          int LSTEPS = (EARLY_BARRIER ? 2 : 3)>
 __device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
@@ -190,8 +203,8 @@ __device__ __forceinline__ void gemm_tile(
   constexpr int NM = TM * TN, NF = TM + TN, LOADS = A_LOADS + B_LOADS;
   constexpr int PER = (LOADS + LSTEPS - 1) / LSTEPS;  // loads per loading step
   constexpr int SP = NM / PER;                        // MFMAs per load
-  constexpr int BAR = (NM - NF) < 5 ? (NM - NF) : 5;  // MFMAs before the barrier
-  static_assert(KS % 2 == 0 && NM >= NF, "schedule shape");
+  constexpr int BAR = (NM - NF) < 5 ? ((NM - NF) > 0 ? (NM - NF) : 0) : 5;  // MFMAs before it
+  static_assert(KS % 2 == 0 && (!EARLY_BARRIER || BAR + NF <= NM), "schedule shape");
   static_assert(LSTEPS <= (EARLY_BARRIER ? KS - 1 : KS), "loads land before the barrier");
   static_assert(SP >= 1 && PER * LSTEPS >= LOADS, "loads fit the MFMA slots");
 
@@ -229,7 +242,15 @@ __device__ __forceinline__ void gemm_tile(
         }
         const int i = idx / TN, j = idx % TN;
         acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[F][i], fb[F][j], acc[i][j], 0, 0, 0);
-        if (kk + 1 < KS && idx < NF) fread1(buf, kk + 1, F ^ 1, idx);
+        if (kk + 1 < KS) {
+          // next step's fragments: one after each MFMA, the rest after the last
+          if (idx + 1 < NM) {
+            if (idx < NF) fread1(buf, kk + 1, F ^ 1, idx);
+          } else {
+#pragma unroll
+            for (int q = idx; q < NF; ++q) fread1(buf, kk + 1, F ^ 1, q);
+          }
+        }
         if (MORE && kk < LSTEPS && idx % SP == SP - 1) {
           const int g = kk * PER + idx / SP;
           if (g < LOADS) gload1(buf ^ 1, knext, g);

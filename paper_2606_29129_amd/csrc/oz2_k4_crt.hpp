@@ -10,7 +10,8 @@
 // slice sum Acc_s = sum_t w_ts U_t < 20 * 2^39 * 255 < 2^52 is exact.  The
 // quotient Q = round(X / P) (< 2^13) is estimated from a rounded X; every
 // R_s = Acc_s - Q P_s is exact, carries are propagated exactly, and an exact
-// signed comparison with P/2 corrects a quotient that is off by one.  The
+// signed comparison with P/2 corrects a quotient that is off by one (skipped
+// when a rounded value of R already shows |R| < P/4).  The
 // magnitude is then rounded once, to nearest even, at the bit position that
 // the output format (binary64 or binary32, subnormals included) dictates.
 #pragma once
@@ -56,7 +57,13 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
   for (int s = 0; s < S; ++s) R[s] = fma(-Q, T.P[s], acc[s]);
   normalize(R);
   // Bring R into (-P/2, P/2): R = C'' + jP with |j| <= 1 and |C''| < P/2.
-  {
+  // Fast test first: the rounded value r of R is within 2^-52 |r| + 1 of R,
+  // so |r| <= quarterP (< P/4 (1 - 2^-30)) proves |R| < P/2, i.e. R = C''.
+  // Otherwise the exact comparisons with P/2 decide.
+  double r = R[S - 1];
+#pragma unroll
+  for (int s = S - 2; s >= 0; --s) r = fma(r, 0x1p39, R[s]);
+  if (!(fabs(r) <= T.quarterP)) {
     double D[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) D[s] = R[s] - T.H[s];
@@ -109,7 +116,7 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
       else if (s < sstar && f != 0.0) rest = true;
     }
     const double cmp = ftop - 0.5;
-    const bool odd = fmod(Tq, 2.0) != 0.0;
+    const bool odd = floor(Tq * 0.5) * 2.0 != Tq;   // Tq < 2^53: an exact integer
     const bool up = cmp > 0.0 || (cmp == 0.0 && (rest || odd));
     res = ldexp(Tq + (up ? 1.0 : 0.0), q - E);
   }

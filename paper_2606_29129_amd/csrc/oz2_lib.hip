@@ -65,10 +65,50 @@ struct Layout {
   size_t e1A, e1B, cmaxA, cmaxB, barA, barB;  // accurate mode only
 };
 
-Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t tile = kBM) {
+// GEMM tile configurations (OZ2_TILE_*): rows x columns of the output tile.
+constexpr int kTileBM[4] = {0, 256, 128, 256};
+constexpr int kTileBN[4] = {0, 256, 128, 64};
+int g_tile_policy = OZ2_TILE_AUTO;
+
+// Automatic tile choice: a cost model over the padded work and the number of
+// workgroup rounds.  A 256 x 256 tile runs one workgroup per CU, the smaller
+// tiles two.  Per CU and unit of padded output the smaller tiles are slower
+// (128 x 128 at 0.80, 256 x 64 at 0.50 of the 256 x 256 rate), but with two
+// workgroups per CU one's prologue and epilogue overlap the other's main
+// loop, while a 256 x 256 round pays them in full (counted as 4 k slabs).
+// The constants are the fit (autotune.fit_tile_model) to measured times of
+// the three tiles (autotune_tiles.json) on 13 shapes
+// (square 512..16384, k from 512 to 16384, n = 64..256 skinny) at N = 14
+// and 20: the model's pick is never more than 0.5% slower than the best.
+int choose_tile(int64_t m, int64_t n, int64_t k, int N) {
+  constexpr double kRate[4] = {0.0, 1.0, 0.80, 0.50};
+  constexpr int kPerCU[4] = {0, 1, 2, 2};
+  constexpr double kFixed[4] = {0.0, 4.0, 0.0, 0.0};
+  const double slabs = (double)((k + kBK - 1) / kBK);
+  int best = OZ2_TILE_256x256;
+  double best_t = 0.0;
+  for (int c = OZ2_TILE_256x256; c <= OZ2_TILE_256x64; ++c) {
+    const int64_t tiles = ((m + kTileBM[c] - 1) / kTileBM[c]) * ((n + kTileBN[c] - 1) / kTileBN[c]);
+    const double rounds = ceil((double)(tiles * N) / (256.0 * kPerCU[c]));
+    const double t =
+        rounds * (double)kTileBM[c] * kTileBN[c] * kPerCU[c] * (slabs + kFixed[c]) / kRate[c];
+    if (c == OZ2_TILE_256x256 || t < best_t) {
+      best = c;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
+int tile_config(int64_t m, int64_t n, int64_t k, int N) {
+  return g_tile_policy == OZ2_TILE_AUTO ? choose_tile(m, n, k, N) : g_tile_policy;
+}
+
+Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm = kBM,
+                   int64_t bn = kBN) {
   Layout L;
-  L.Mp = round_up(m > 0 ? m : 1, tile);
-  L.Np = round_up(n > 0 ? n : 1, tile);
+  L.Mp = round_up(m > 0 ? m : 1, bm);
+  L.Np = round_up(n > 0 ? n : 1, bn);
   L.Kp = round_up(k > 0 ? k : 1, kBK);
   L.nch = (k + kKC - 1) / kKC;
   size_t off = 0;
@@ -213,6 +253,30 @@ void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, i
       B, ldb, n, k, (const int32_t*)(ws + L.eB), tab, N, (int8_t*)(ws + L.RB), L.Np, L.Kp);
 }
 
+// K3 over the planes given by (t, planes): EPI 0 runs all N planes (t
+// ignored), EPI 1 and 2 one plane.
+template <int EPI>
+void launch_gemm(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* U, int32_t* aux0,
+                 int32_t* aux1, int64_t m, int64_t n, const Layout& L, const ModTable* tab,
+                 int t, int planes) {
+  const unsigned tiles =
+      (unsigned)((L.Mp / kTileBM[cfg]) * (L.Np / kTileBN[cfg]) * planes);
+  switch (cfg) {
+    case OZ2_TILE_128x128:
+      k3_gemm_i8<128, 128, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
+                                                                 L.Mp, L.Np, L.Kp, tab, t);
+      break;
+    case OZ2_TILE_256x64:
+      k3_gemm_i8<256, 64, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
+                                                                L.Mp, L.Np, L.Kp, tab, t);
+      break;
+    default:
+      k3_gemm_i8<256, 256, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
+                                                                 L.Mp, L.Np, L.Kp, tab, t);
+      break;
+  }
+}
+
 template <int S, typename TO>
 void launch_crt(const Layout& L, char* ws, const ModTable* tab, int N, int64_t m, int64_t n,
                 TO* C, int64_t ldc) {
@@ -243,7 +307,8 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   const ModTable& HT = g_host_tables[acc_tab][N];
   const ModTable* tab = D.d_tables + acc_tab * (kMaxN + 1) + N;
 
-  Layout L = make_layout(m, n, k, N, mode);
+  const int cfg = tile_config(m, n, k, N);
+  Layout L = make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg]);
   char* ws = nullptr;
   if ((rc = get_workspace(dev, L.total, &ws))) return rc;
 
@@ -276,20 +341,18 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
           (double*)(ws + L.partA), pmA, L.nch, m, e1A, (int*)(ws + L.status));
       k1_fold_first<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
           (double*)(ws + L.partB), pmB, L.nch, n, e1B, (int*)(ws + L.status));
-      dim3 gb((unsigned)(L.Mp / 256), (unsigned)(L.Kp / 128));
+      dim3 gb((unsigned)(L.Mp / kK2VB), (unsigned)(L.Kp / kK2HB));
       k2_bar_strided<T><<<gb, 256, 0, g_stream>>>(A, lda, m, k, e1A, (int8_t*)(ws + L.barA),
                                                   L.Mp, L.Kp);
-      int64_t wb = L.Np * (L.Kp / 16);
+      int64_t wb = L.Np * (L.Kp / kK2EPT);
       k2_bar_contig<T><<<(unsigned)((wb + 255) / 256), 256, 0, g_stream>>>(
           B, ldb, n, k, e1B, (int8_t*)(ws + L.barB), L.Np, L.Kp);
       int32_t* cmA = (int32_t*)(ws + L.cmaxA);
       int32_t* cmB = (int32_t*)(ws + L.cmaxB);
       k_fill_i32<<<(unsigned)((L.Mp + 255) / 256), 256, 0, g_stream>>>(cmA, L.Mp, 0);
       k_fill_i32<<<(unsigned)((L.Np + 255) / 256), 256, 0, g_stream>>>(cmB, L.Np, 0);
-      const int tiles1 = (int)((L.Mp / kBM) * (L.Np / kBN));
-      k3_gemm_i8<kBM, kBN, kBK, 2><<<(unsigned)tiles1, 256, 0, g_stream>>>(
-          (const int8_t*)(ws + L.barA), (const int8_t*)(ws + L.barB), nullptr, cmA, cmB, m, n,
-          L.Mp, L.Np, L.Kp, tab, 0);
+      launch_gemm<2>(cfg, (const int8_t*)(ws + L.barA), (const int8_t*)(ws + L.barB), nullptr,
+                     cmA, cmB, m, n, L, tab, 0, 1);
       k1_accurate_exponent<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
           e1A, cmA, m, tab, (int32_t*)(ws + L.eA));
       k1_accurate_exponent<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
@@ -310,16 +373,13 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   }
   clk.mark(2);
   // K3: N INT8 GEMMs.
-  const int tiles = (int)((L.Mp / kBM) * (L.Np / kBN));
   if (dbg) {
     if (dbg->Ct)
-      k3_gemm_i8<kBM, kBN, kBK, 1><<<(unsigned)tiles, 256, 0, g_stream>>>(
-          (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr, dbg->Ct, nullptr, m,
-          n, L.Mp, L.Np, L.Kp, tab, dbg->t);
+      launch_gemm<1>(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr,
+                     dbg->Ct, nullptr, m, n, L, tab, dbg->t, 1);
   } else {
-    k3_gemm_i8<kBM, kBN, kBK, 0><<<(unsigned)(tiles * N), 256, 0, g_stream>>>(
-        (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), (uint8_t*)(ws + L.U), nullptr,
-        nullptr, m, n, L.Mp, L.Np, L.Kp, tab, 0);
+    launch_gemm<0>(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB),
+                   (uint8_t*)(ws + L.U), nullptr, nullptr, m, n, L, tab, 0, N);
   }
   clk.mark(3);
   // K4: CRT and unscaling.
@@ -437,7 +497,7 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
   sig = mix64(sig, (uint64_t)dev);
   for (int a = 0; a < na; ++a) {
     const oz2_problem& q = P[act[a]];
-    lay[a] = make_layout(q.m, q.n, q.k, q.N, mode, kBatchTile);
+    lay[a] = make_layout(q.m, q.n, q.k, q.N, mode, kBatchTile, kBatchTile);
     base[a] = total;
     total += lay[a].total;
     nitems += (int64_t)q.N * (lay[a].Mp / kBatchTile) * (lay[a].Np / kBatchTile);
@@ -711,6 +771,22 @@ int ozaki2_query_constants(int N, int32_t* moduli, float* p_prime_prop, float* p
   if (p_prime_fast) *p_prime_fast = T.p_fast;
   if (delta) *delta = T.delta;
   if (log2_P) *log2_P = T.log2P;
+  return 0;
+}
+
+int ozaki2_set_tile(int tile) {
+  if (tile < OZ2_TILE_AUTO || tile > OZ2_TILE_256x64) return -1;
+  g_tile_policy = tile;
+  return 0;
+}
+
+int ozaki2_get_tile(int64_t m, int64_t n, int64_t k, int N, int* tile) {
+  if (m < 0) return -1;
+  if (n < 0) return -2;
+  if (k < 0) return -3;
+  if (N < OZ2_N_MIN || N > OZ2_N_MAX) return -4;
+  if (!tile) return -5;
+  *tile = tile_config(m, n, k, N);
   return 0;
 }
 

@@ -31,6 +31,7 @@ struct ModTable {
   double P[kMaxSlices];            // P in 39-bit slices
   double H[kMaxSlices];            // P/2 in 39-bit slices
   double invP;                     // RN(1/P), only for quotient estimates
+  double quarterP;                 // a binary64 value a little below P/4
   float p_prop;                    // P'_prop = RD32(log2(P-1)/2 - 0.5)
   float p_fast;                    // P'_fast = RD32(log2(P-1)/2 - 1.5)
   float delta;                     // RU32(0.5 / (1 - 4 u32))
@@ -175,6 +176,7 @@ inline bool build_table(int N, bool accurate_limbs, ModTable* T) {
   long double log2P = P.log2l_approx();
   T->log2P = (double)log2P;
   T->invP = (double)exp2l(-log2P);
+  T->quarterP = (double)(exp2l(log2P - 2.0L) * (1.0L - 0x1p-30L));
   long double log2Pm1 = P.sub_small(1).log2l_approx();
   if (!round_f32_checked(log2Pm1 / 2 - 0.5L, false, &T->p_prop)) return false;
   if (!round_f32_checked(log2Pm1 / 2 - 1.5L, false, &T->p_fast)) return false;

@@ -47,6 +47,8 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(ctypes.c_double)], _c_int),
     "ozaki2_set_timing": ([_c_int], _c_int),
+    "ozaki2_set_tile": ([_c_int], _c_int),
+    "ozaki2_get_tile": ([_c_i64] * 3 + [_c_int, ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_get_stage_times": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_debug_stages": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _c_int, _c_int, _c_int]
                             + [_vp] * 7, _c_int),
@@ -148,6 +150,19 @@ def ozaki2_query_constants(N):
         N, mod, ctypes.byref(pp), ctypes.byref(pf), ctypes.byref(d), ctypes.byref(lp)))
     return dict(moduli=list(mod[:N]), p_prime_prop=pp.value, p_prime_fast=pf.value,
                 delta=d.value, log2_P=lp.value)
+
+
+TILE_AUTO, TILE_256x256, TILE_128x128, TILE_256x64 = 0, 1, 2, 3
+
+
+def ozaki2_set_tile(tile):
+    return lib().ozaki2_set_tile(tile)
+
+
+def ozaki2_get_tile(m, n, k, N):
+    t = ctypes.c_int(0)
+    _check("ozaki2_get_tile", lib().ozaki2_get_tile(m, n, k, N, ctypes.byref(t)))
+    return t.value
 
 
 def ozaki2_set_timing(enable):

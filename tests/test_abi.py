@@ -82,3 +82,24 @@ def test_workspace_size_grows_with_problem():
     c = oz.ozaki2_workspace_size(1024, 1024, 1024, 20)
     assert 0 < a < b < c
     assert oz.ozaki2_workspace_size(0, 10, 10, 14) == 0
+
+
+def test_tile_policy_and_automatic_choice():
+    """ozaki2_set_tile validates its argument; the automatic choice is
+    deterministic host logic: the wide tile for large squares, the narrow one
+    for n = 64."""
+    assert oz.ozaki2_set_tile(7) == -1
+    assert oz.ozaki2_set_tile(-1) == -1
+    assert oz.ozaki2_set_tile(oz.TILE_AUTO) == 0
+    assert oz.ozaki2_get_tile(16384, 16384, 16384, 14) == oz.TILE_256x256
+    assert oz.ozaki2_get_tile(8192, 8192, 8192, 14) == oz.TILE_256x256
+    assert oz.ozaki2_get_tile(65536, 64, 4096, 14) == oz.TILE_256x64
+    for t in (oz.TILE_256x256, oz.TILE_128x128, oz.TILE_256x64):
+        assert oz.ozaki2_set_tile(t) == 0
+        assert oz.ozaki2_get_tile(16384, 16384, 16384, 14) == t
+    assert oz.ozaki2_set_tile(oz.TILE_AUTO) == 0
+    t = ctypes.c_int(0)
+    lib = oz.lib()
+    assert lib.ozaki2_get_tile(1, 1, 1, 1, ctypes.byref(t)) == -4
+    assert lib.ozaki2_get_tile(-1, 1, 1, 14, ctypes.byref(t)) == -1
+    assert lib.ozaki2_get_tile(1, 1, 1, 14, None) == -5

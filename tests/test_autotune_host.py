@@ -1,4 +1,5 @@
 """Host-side logic of the N autotuner (CPU only)."""
+import json
 import math
 from fractions import Fraction
 
@@ -42,3 +43,20 @@ def test_pick_N_is_monotone_in_target_k_and_phi():
     assert autotune.pick_N(256, 0.5, 1e-15, tab) <= autotune.pick_N(256, 3.0, 1e-15, tab)
     # beyond the grid and unreachable targets
     assert autotune.pick_N(10**6, 9.0, 1e-300, tab) == 20
+
+
+def test_library_tile_choice_matches_measurements():
+    """The library's automatic tile (ozaki2_get_tile, host logic) is within
+    2% of the fastest forced tile on every measured shape, and the committed
+    fit reproduces the library's constants."""
+    from paper_2606_29129_amd import ozaki2 as oz
+    with open(autotune.TILE_TABLE) as f:
+        table = json.load(f)
+    for rec in table["shapes"]:
+        for N in table["Ns"]:
+            ms = {t: rec["ms"][f"{N}/{t}"] for t in autotune.TILES}
+            pick = oz.ozaki2_get_tile(rec["m"], rec["n"], rec["k"], N)
+            assert ms[pick] <= 1.02 * min(ms.values()), (rec["m"], rec["n"], rec["k"], N, pick)
+    rate, fixed, tot, worst = autotune.fit_tile_model(table)
+    assert rate == {1: 1.0, 2: 0.8, 3: 0.5} and fixed == {1: 4, 2: 0, 3: 0}
+    assert worst < 0.01

@@ -138,7 +138,8 @@ def test_leading_dimensions_and_padding_rows():
 
 @pytest.mark.parametrize("s", [300, -300])
 def test_power_of_two_scaling_is_exact(s):
-    """Section 4: A -> 2**s A scales C by exactly 2**s, on the GPU."""
+    """Section 4: A -> 2**s A scales C by exactly 2**s, on the GPU (every
+    row of this seeded input has an exactly shifted Algorithm 2 exponent)."""
     A, B = inputs.problem(96, 64, 160, 1.0, seed=8)
     C0 = _gpu_dgemm(A, B, 14)
     C1 = _gpu_dgemm(A * 2.0 ** s, B, 14)
@@ -285,3 +286,23 @@ def test_accurate_mode_parity(m, n, k, phi, N, seed):
         assert np.array_equal(g["RB"][t], r["RB"][t].T)
     assert np.array_equal(g["Ct"].astype(np.int64), r["G"][N - 1])
     assert _bits_equal(_gpu_dgemm(A, B, N, mode=2), r["C"])
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_every_tile_shape_gives_the_same_bits(tile, mode):
+    """Each forced GEMM tile (256x256, 128x128, 256x64) on a shape that is
+    ragged for all of them: INT32 products through the debug hook and C equal
+    the oracle bit for bit, in every mode."""
+    m, n, k, N = 300, 70, 200, 14
+    print(f"case tile={tile} mode={mode} m={m} n={n} k={k} N={N}", flush=True)
+    A, B = inputs.problem(m, n, k, 1.0, 41 + tile)
+    which = (ref.REVISED, ref.ORIGINAL, ref.ACCURATE)[mode]
+    r = ref.gemm(A, B, N, which)
+    assert oz.ozaki2_set_tile(tile) == 0
+    try:
+        g = _gpu_stages(A, B, N, mode, N - 1)
+        assert np.array_equal(g["Ct"].astype(np.int64), r["G"][N - 1])
+        assert _bits_equal(_gpu_dgemm(A, B, N, mode=mode), r["C"])
+    finally:
+        oz.ozaki2_set_tile(0)

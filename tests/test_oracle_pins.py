@@ -125,7 +125,10 @@ def test_integer_inputs_give_the_exact_product(N):
 
 def test_scale_invariance_powers_of_two():
     """Section 4: A -> 2**s A leaves A' unchanged and scales C by exactly
-    2**s (s = +-300); the original fast mode changes A'."""
+    2**s (s = +-300) for every row whose exponent Algorithm 2 shifts exactly
+    (all rows of this seeded input; the binary32 rounding of w can lower an
+    exponent by one at such scales, see test_oracle_scaling); the original
+    fast mode changes A'."""
     A, B = inputs.problem(6, 5, 40, 1.0, seed=3)
     r0 = ozaki2.gemm(A, B, 14)
     for s in (300, -300):
