@@ -106,6 +106,12 @@ __device__ __forceinline__ void wait_vmem_all() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #endif
 }
+template <int N>
+__device__ __forceinline__ void wait_vmem_n() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+#endif
+}
 __device__ __forceinline__ void wait_vmem_lds_all() {
 #if defined(__HIP_DEVICE_COMPILE__)
   asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
@@ -121,8 +127,11 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 // bubble of the matrix core:
 //   * in k step kk, the TM + TN fragment reads of step kk + 1 follow the
 //     first TM + TN MFMAs, one after each;
-//   * the next slab's global->LDS loads are spread over k steps 0 and 1,
-//     evenly among their MFMAs (so they have two steps to land);
+//   * the next slab's global->LDS loads: half of them ride on MFMAs of the
+//     previous slab's last k step right after its barrier (the buffer they
+//     fill is free from then on), the other half on k steps 0 and 1, so they
+//     have two to four k steps to land (measured 1-4% faster than issuing
+//     all of them in k steps 0 and 1);
 //   * in the last k step, after a few MFMAs, the wave waits for its own
 //     loads and LDS reads and meets the others at the slab barrier; the
 //     next slab is then complete in LDS and the current buffer is free, and
@@ -138,7 +147,7 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 // per k step and two workgroups per CU, keep the barrier at the top of the
 // slab and spread the loads over three k steps (measured best for them).
 template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = (BM >= 256 && BN >= 256),
-          int LSTEPS = (EARLY_BARRIER ? 2 : 3)>
+          int LSTEPS = (EARLY_BARRIER ? 2 : 3), int LX = (EARLY_BARRIER ? 8 : 0)>
 __device__ __forceinline__ void gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
@@ -200,28 +209,43 @@ __device__ __forceinline__ void gemm_tile(
     }
   };
 
+  // LX (early-barrier mode only): the first LX loads of slab kt + 2 are
+  // issued in slab kt's last k step right after the barrier (the buffer of
+  // slab kt is free from then on), giving them about four k steps to land;
+  // the other LOADS - LX loads of a slab go out in k steps 0..LSTEPS-1 of the
+  // slab before it.
   constexpr int NM = TM * TN, NF = TM + TN, LOADS = A_LOADS + B_LOADS;
-  constexpr int PER = (LOADS + LSTEPS - 1) / LSTEPS;  // loads per loading step
-  constexpr int SP = NM / PER;                        // MFMAs per load
+  constexpr int LY = LOADS - LX;                      // loads in steps 0..LSTEPS-1
+  constexpr int PER = (LY + LSTEPS - 1) / LSTEPS;     // loads per loading step
+  constexpr int SP = PER > 0 ? NM / PER : NM;         // MFMAs per load
   constexpr int BAR = (NM - NF) < 5 ? ((NM - NF) > 0 ? (NM - NF) : 0) : 5;  // MFMAs before it
   static_assert(KS % 2 == 0 && (!EARLY_BARRIER || BAR + NF <= NM), "schedule shape");
   static_assert(LSTEPS <= (EARLY_BARRIER ? KS - 1 : KS), "loads land before the barrier");
-  static_assert(SP >= 1 && PER * LSTEPS >= LOADS, "loads fit the MFMA slots");
+  static_assert(SP >= 1 && PER * LSTEPS >= LY, "loads fit the MFMA slots");
+  static_assert(LX == 0 || (EARLY_BARRIER && LX <= NM - BAR - 1 && LX <= 63), "early loads");
 
   const int nk = (int)(Kp / BK);
 #pragma unroll
   for (int i = 0; i < LOADS; ++i) gload1(0, 0, i);
   if constexpr (EARLY_BARRIER) {
-    wait_vmem_all();
+    if (LX > 0 && nk > 1) {
+#pragma unroll
+      for (int i = 0; i < LX; ++i) gload1(1, BK, i);
+      wait_vmem_n<LX>();  // slab 0 has landed; slab 1's first loads may not
+    } else {
+      wait_vmem_all();
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NF; ++q) fread1(0, 0, 0, q);
   }
-  // One slab; MORE = false for the last one, which has no next slab to load
-  // or to read ahead (a separate copy, so that both stay one basic block).
+  // One slab.  MORE: a next slab exists (load the rest of it, meet at the
+  // barrier, read ahead); MORE2: a slab after that exists (its first LX
+  // loads).  Separate copies, so that each stays one basic block.
   int buf = 0;
-  auto slab = [&](int kt, auto more_tag) {
+  auto slab = [&](int kt, auto more_tag, auto more2_tag) {
     constexpr bool MORE = decltype(more_tag)::value;
+    constexpr bool MORE2 = decltype(more2_tag)::value;
     const int64_t knext = (int64_t)(kt + 1) * BK;
     if constexpr (!EARLY_BARRIER) {
       // Barrier at the top of the slab: slab kt is in LDS and every wave is
@@ -251,19 +275,23 @@ __device__ __forceinline__ void gemm_tile(
             for (int q = idx; q < NF; ++q) fread1(buf, kk + 1, F ^ 1, q);
           }
         }
-        if (MORE && kk < LSTEPS && idx % SP == SP - 1) {
-          const int g = kk * PER + idx / SP;
+        if (MORE && kk < LSTEPS && PER > 0 && idx % SP == SP - 1) {
+          const int g = LX + kk * PER + idx / SP;
           if (g < LOADS) gload1(buf ^ 1, knext, g);
         }
         if (MORE && EARLY_BARRIER && kk == KS - 1 && idx >= BAR && idx < BAR + NF)
           fread1(buf ^ 1, 0, 0, idx - BAR);
+        if (MORE2 && LX > 0 && kk == KS - 1 && idx > BAR && idx <= BAR + LX)
+          gload1(buf, knext + BK, idx - BAR - 1);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
     buf ^= 1;
   };
-  for (int kt = 0; kt + 1 < nk; ++kt) slab(kt, std::true_type{});
-  slab(nk - 1, std::false_type{});
+  int kt = 0;
+  for (; kt + 2 < nk; ++kt) slab(kt, std::true_type{}, std::true_type{});
+  if (nk >= 2) slab(nk - 2, std::true_type{}, std::false_type{});
+  slab(nk - 1, std::false_type{}, std::false_type{});
   wait_vmem_all();  // no load may still target LDS when the tile returns
 
   const int64_t Mb = Mp / 32;

@@ -3,6 +3,7 @@
     python -m paper_2606_29129_amd.profiling stats DIR TITLE COMMAND > summary.md
     python -m paper_2606_29129_amd.profiling traffic FETCH_DIR WRITE_DIR COMMAND \
         --workload "m=16384 n=16384 k=16384 N=14" --copy-bytes B > traffic.txt
+    python -m paper_2606_29129_amd.profiling counters COMMAND DIR... --ms T --ops X
 
 ``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
 --stats --output-format csv`` writes and prints a short markdown table of the
@@ -144,6 +145,62 @@ def traffic_text(fetch_dir: str, write_dir: str, cmd: str, workload: str, copy_b
     return "\n".join(lines) + "\n"
 
 
+def counters_markdown(dirs, cmd: str, kernel: str, ms_per_launch: float, ops_per_launch: float,
+                      cus: int = 256, xcds: int = 8, peak_tops: float = 5000.0) -> str:
+    """Per-dispatch means of every counter collected for the kernel over the
+    given ``--pmc`` runs, plus derived figures: the shader clock
+    (GRBM_GUI_ACTIVE, summed over the XCDs, over the launch time), the MFMA
+    busy fraction (SQ_VALU_MFMA_BUSY_CYCLES over SQ_BUSY_CU_CYCLES x 4 SIMDs),
+    the fraction of wave cycles spent in s_waitcnt and the achieved fraction
+    of the INT8 MFMA peak."""
+    vals = {}
+    for d in dirs:
+        for path in _find(d, "counter_collection.csv"):
+            per = defaultdict(float)
+            names = {}
+            with open(path, newline="") as f:
+                for r in csv.DictReader(f):
+                    if kernel not in r["Kernel_Name"]:
+                        continue
+                    key = (r["Counter_Name"], r["Dispatch_Id"])
+                    per[key] += float(r["Counter_Value"])
+            sums, counts = defaultdict(float), defaultdict(int)
+            for (cname, _), v in per.items():
+                sums[cname] += v
+                counts[cname] += 1
+            for cname in sums:
+                vals[cname] = (sums[cname] / counts[cname], counts[cname])
+    out = [f"# Counters of `{kernel}` (rocprofv3 --pmc)", "", "Command (run from the repository "
+           "root on one MI355X; one run per counter group):", "", "```", cmd, "```", "",
+           "| counter | mean per dispatch | dispatches |", "|---|---|---|"]
+    for cname in sorted(vals):
+        v, c = vals[cname]
+        out.append(f"| {cname} | {v:.6g} | {c} |")
+    out.append("")
+    gui = vals.get("GRBM_GUI_ACTIVE", (None, 0))[0]
+    cu_cycles = vals.get("SQ_BUSY_CU_CYCLES", (None, 0))[0]
+    if gui:
+        out.append(f"* shader clock: GRBM_GUI_ACTIVE / ({xcds} XCDs x launch time) = "
+                   f"{gui / xcds / (ms_per_launch * 1e-3) / 1e9:.3f} GHz (the counter is "
+                   f"summed over the XCDs; launch time {ms_per_launch} ms from the kernel trace)")
+    if cu_cycles:
+        out.append(f"* busy cycles per CU: SQ_BUSY_CU_CYCLES / {cus} = {cu_cycles / cus:.4g} "
+                   f"({cu_cycles / cus / (ms_per_launch * 1e-3) / 1e9:.3f} GHz over the launch)")
+        busy = vals.get("SQ_VALU_MFMA_BUSY_CYCLES", (None, 0))[0]
+        if busy:
+            out.append(f"* MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / (SQ_BUSY_CU_CYCLES x 4 SIMDs) = "
+                       f"{busy / (cu_cycles * 4):.4f}")
+        wait = vals.get("SQ_WAIT_ANY", (None, 0))[0]
+        wave = vals.get("SQ_WAVE_CYCLES", (None, 0))[0]
+        if wait and wave:
+            out.append(f"* waves waiting (s_waitcnt): SQ_WAIT_ANY / SQ_WAVE_CYCLES = {wait / wave:.4f}")
+    out.append(f"* achieved INT8 rate: {ops_per_launch:.4g} ops / {ms_per_launch} ms = "
+               f"{ops_per_launch / (ms_per_launch * 1e-3) / 1e12:.1f} TOP/s = "
+               f"{ops_per_launch / (ms_per_launch * 1e-3) / 1e12 / peak_tops:.4f} of "
+               f"{peak_tops:.0f} TOP/s")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -157,8 +214,16 @@ def main(argv=None):
     t.add_argument("command")
     t.add_argument("--workload", required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("command")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel", default=K3_NAME)
+    c.add_argument("--ms", type=float, required=True, help="average launch time, ms")
+    c.add_argument("--ops", type=float, required=True, help="algorithmic ops per launch")
     a = ap.parse_args(argv)
-    if a.what == "stats":
+    if a.what == "counters":
+        sys.stdout.write(counters_markdown(a.dirs, a.command, a.kernel, a.ms, a.ops))
+    elif a.what == "stats":
         sys.stdout.write(stats_markdown(a.dir, a.title, a.command))
     else:
         sys.stdout.write(traffic_text(a.fetch_dir, a.write_dir, a.command, a.workload,
