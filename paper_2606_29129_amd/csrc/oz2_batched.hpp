@@ -34,33 +34,27 @@ struct BatchProb {
   int64_t k1a_gx;  // K1 strided grid width (height is ceil(nch/4))
 };
 
+// k slab of the batched GEMM tile (bytes).
+constexpr int kBatchBK = 64;
+
 // The fast modes need at most 3 limbs of 26 bits for |a'| (< 2^78 at N = 20).
 constexpr int kBatchLimbs = 3;
 
 // Stages with a per-problem block count.
 enum BatchStage { kB_K1A = 0, kB_K1B, kB_FOLDA, kB_FOLDB, kB_K2A, kB_K2B, kB_K4, kB_NSTAGES };
 
-// Problem owning global block `b`: largest p with prefix[p] <= b.
-__device__ __forceinline__ int find_problem(const int64_t* __restrict__ prefix, int batch,
-                                            int64_t b) {
-  int lo = 0, hi = batch - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // One instantiation per stage, so that each gets the register budget (and
 // occupancy) of its own body.
+// A block finds its problem in a host-built table (one load) and its
+// position inside the problem from the stage's block prefix sums.
 template <int STAGE>
 __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ probs,
-                                                const int64_t* __restrict__ prefix, int batch,
+                                                const int64_t* __restrict__ prefix,
+                                                const uint16_t* __restrict__ owner, int batch,
                                                 int* __restrict__ status) {
   const int64_t* pre = prefix + (int64_t)STAGE * (batch + 1);
   const int64_t b = blockIdx.x;
-  const int p = find_problem(pre, batch, b);
+  const int p = owner[b];
   const int64_t local = b - pre[p];
   const BatchProb& P = probs[p];
   switch (STAGE) {
@@ -104,33 +98,54 @@ struct WorkItem {
   uint16_t tn;
 };
 
+// Persistent GEMM over the work list (sorted by decreasing k).  Workgroup b
+// takes items b, b + G, b + 2G, ... (G = grid size): a sorted list dealt out
+// round-robin balances like a greedy queue, without the contended atomic
+// counter, and the next item is known in advance, so its descriptor is
+// loaded while the current tile runs.
+struct TileArgs {
+  const int8_t* RA;
+  const int8_t* RB;
+  uint8_t* U;
+  int64_t m, n, Mp, Np, Kp;
+  const ModTable* tab;
+  int t, tm, tn;
+};
+
+__device__ __forceinline__ TileArgs tile_args(const BatchProb* __restrict__ probs,
+                                              const WorkItem* __restrict__ items, int i) {
+  const WorkItem w = items[i];
+  const BatchProb& P = probs[w.p];
+  return TileArgs{P.RA, P.RB, P.U, P.m, P.n, P.Mp, P.Np, P.Kp, P.tab, w.t, w.tm, w.tn};
+}
+
 __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ probs,
-                                               const WorkItem* __restrict__ items, int nitems,
-                                               int* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[2][2 * kBatchTile * 128];
-  __shared__ int next;
+                                               const WorkItem* __restrict__ items, int nitems) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[2][2 * kBatchTile * kBatchBK];
+  int i = blockIdx.x;
+  if (i >= nitems) return;
+  TileArgs cur = tile_args(probs, items, i);
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int i = next;
-    __syncthreads();
-    if (i >= nitems) break;
-    const WorkItem w = items[i];
-    const BatchProb& P = probs[w.p];
-    // A 128 x 128 tile has only 4 MFMAs per k step per wave, and two
-    // workgroups share a CU: the slab-top barrier with the next slab's loads
-    // spread over three k steps measured best for it.
-    gemm_tile<kBatchTile, kBatchTile, 128, 0, false, 3>(P.RA, P.RB, P.U, nullptr, nullptr, P.m,
-                                                        P.n, P.Mp, P.Np, P.Kp, P.tab, w.t, w.tm,
-                                                        w.tn, lds);
+    const int inext = i + (int)gridDim.x;
+    const bool more = inext < nitems;
+    const TileArgs nxt = tile_args(probs, items, more ? inext : i);
+    // A 128 x 128 tile has only 4 MFMAs per k step per wave; with 64-byte
+    // k slabs (32 KiB of LDS) three workgroups share a CU, hiding the
+    // per-item latency of the small problems; barrier at the slab top.
+    gemm_tile<kBatchTile, kBatchTile, kBatchBK, 0, false, 2>(cur.RA, cur.RB, cur.U, nullptr, nullptr,
+                                                        cur.m, cur.n, cur.Mp, cur.Np, cur.Kp,
+                                                        cur.tab, cur.t, cur.tm, cur.tn, lds);
+    if (!more) break;
+    __syncthreads();  // every wave is done with the LDS before the next prologue
+    i = inext;
+    cur = nxt;
   }
 }
 
-__global__ void kb_reset(int* __restrict__ counter, int* __restrict__ status) {
-  if (threadIdx.x == 0) {
-    counter[0] = 0;
-    status[0] = 0;
-  }
+// Status word reset at the start of each replay (a kernel, not a memset, so
+// that it can live in the captured graph).
+__global__ void kb_reset(int* __restrict__ status) {
+  if (threadIdx.x == 0) status[0] = 0;
 }
 
 }  // namespace oz2

@@ -140,48 +140,61 @@ __device__ __forceinline__ void k4_crt_body(
   const int64_t nb_used = (n + 31) / 32;
   if (blk >= mb_used * nb_used) return;  // whole wave: the tile is per wave
   const int64_t bi = blk % mb_used, bj = blk / mb_used;
-  double acc[16][S];
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-#pragma unroll
-    for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
   const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16;
   const int64_t plane = Nb * Mb * 1024;
-  for (int t = 0; t < N; ++t) {
-    uint4 w = *reinterpret_cast<const uint4*>(src + (int64_t)t * plane);
-    uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-    double wt[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double u = (double)((ws[r >> 2] >> (8 * (r & 3))) & 0xFFu);
-#pragma unroll
-      for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
-    }
-  }
   const int lc = acc_col(lane);
   const int64_t col = bj * 32 + lc;
   const int32_t f = col < n ? eB[col] : 0;
   const ModTable& T = *tab;
+  // With 4 slices, two passes over the planes, each for 8 of the lane's 16
+  // entries (8 of its 16 bytes per plane): half the accumulator registers
+  // (occupancy), no extra reads.  With fewer slices one pass.
+  constexpr int PASSES = S >= 4 ? 2 : 1, R = 16 / PASSES;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int lr = acc_row(r, lane);
-    const int64_t row = bi * 32 + lr;
-    double v = 0.0;
-    if (row < m && col < n) {
-      const int32_t e = eA[row];
-      if (e == kExpNonFinite || f == kExpNonFinite) {
-        v = __builtin_nan("");
+  for (int h = 0; h < PASSES; ++h) {
+    double acc[R][S];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
+    for (int t = 0; t < N; ++t) {
+      uint32_t ws[R / 4];
+      if constexpr (R == 16) {
+        const uint4 w = *reinterpret_cast<const uint4*>(src + (int64_t)t * plane);
+        ws[0] = w.x; ws[1] = w.y; ws[2] = w.z; ws[3] = w.w;
       } else {
-        double a[S];
+        const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane + 8 * h);
+        ws[0] = w.x; ws[1] = w.y;
+      }
+      double wt[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) a[s] = acc[r][s];
-        if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
-        else v = crt_unscale<S, 24, -149>(a, T, e + f);
+      for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double u = (double)((ws[r >> 2] >> (8 * (r & 3))) & 0xFFu);
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
       }
     }
-    tile[wave][lc][lr] = (TO)v;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int lr = acc_row(R * h + r, lane);
+      const int64_t row = bi * 32 + lr;
+      double v = 0.0;
+      if (row < m && col < n) {
+        const int32_t e = eA[row];
+        if (e == kExpNonFinite || f == kExpNonFinite) {
+          v = __builtin_nan("");
+        } else {
+          double a[S];
+#pragma unroll
+          for (int s = 0; s < S; ++s) a[s] = acc[r][s];
+          if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
+          else v = crt_unscale<S, 24, -149>(a, T, e + f);
+        }
+      }
+      tile[wave][lc][lr] = (TO)v;
+    }
   }
   // LDS operations of one wave complete in order; the fence keeps the
   // compiler from moving the reads above the writes.

@@ -508,12 +508,44 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
   char* ws = nullptr;
   if ((rc = get_workspace(dev, total, &ws))) return rc;
 
+  int64_t blocks[kB_NSTAGES];
+  // Block prefix sums per stage, and each block's problem.
+  std::vector<int64_t> prefix((size_t)(na + 1) * kB_NSTAGES, 0);
+  for (int st = 0; st < kB_NSTAGES; ++st) {
+    int64_t acc = 0;
+    for (int a = 0; a < na; ++a) {
+      const oz2_problem& q = P[act[a]];
+      const Layout& L = lay[a];
+      int64_t c = 0;
+      switch (st) {
+        case kB_K1A: c = ((q.m + 63) / 64) * ((L.nch + 3) / 4); break;
+        case kB_K1B: c = (q.n * L.nch + 255) / 256; break;
+        case kB_FOLDA: c = (q.m + 255) / 256; break;
+        case kB_FOLDB: c = (q.n + 255) / 256; break;
+        case kB_K2A: c = (L.Mp / kK2VB) * (L.Kp / kK2HB); break;
+        case kB_K2B: c = (L.Np * (L.Kp / kK2EPT) + 255) / 256; break;
+        default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
+      }
+      prefix[(size_t)st * (na + 1) + a] = acc;
+      acc += c;
+    }
+    prefix[(size_t)st * (na + 1) + na] = acc;
+    blocks[st] = acc;
+    if (acc > INT32_MAX) return OZ2_ERR_TOO_LARGE;
+  }
+  int64_t total_blocks = 0;
+  int64_t owner_off[kB_NSTAGES];
+  for (int st = 0; st < kB_NSTAGES; ++st) {
+    owner_off[st] = total_blocks;
+    total_blocks += blocks[st];
+  }
+
   // Metadata layout in the batch-owned device allocation.
-  const size_t off_counter = 0, off_status = 256, off_probs = 512;
+  const size_t off_status = 0, off_probs = 256;
   const size_t off_prefix = off_probs + align256(sizeof(BatchProb) * na);
   const size_t off_items = off_prefix + align256(sizeof(int64_t) * (na + 1) * kB_NSTAGES);
-  const size_t meta_need = off_items + align256(sizeof(WorkItem) * (size_t)nitems);
-  int64_t blocks[kB_NSTAGES];
+  const size_t off_owner = off_items + align256(sizeof(WorkItem) * (size_t)nitems);
+  const size_t meta_need = off_owner + align256(sizeof(uint16_t) * (size_t)total_blocks);
 
   if (!g_batch.valid || g_batch.sig != sig || g_batch.dev != dev) {
     if (g_batch.launched) (void)hipEventSynchronize(g_batch.done);
@@ -537,30 +569,6 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
         return OZ2_ERR_WORKSPACE;
       g_batch.h_cap = na;
     }
-    // Block prefix sums per stage and the GEMM work list (largest k first).
-    std::vector<int64_t> prefix((size_t)(na + 1) * kB_NSTAGES, 0);
-    for (int st = 0; st < kB_NSTAGES; ++st) {
-      int64_t acc = 0;
-      for (int a = 0; a < na; ++a) {
-        const oz2_problem& q = P[act[a]];
-        const Layout& L = lay[a];
-        int64_t c = 0;
-        switch (st) {
-          case kB_K1A: c = ((q.m + 63) / 64) * ((L.nch + 3) / 4); break;
-          case kB_K1B: c = (q.n * L.nch + 255) / 256; break;
-          case kB_FOLDA: c = (q.m + 255) / 256; break;
-          case kB_FOLDB: c = (q.n + 255) / 256; break;
-          case kB_K2A: c = (L.Mp / kK2VB) * (L.Kp / kK2HB); break;
-          case kB_K2B: c = (L.Np * (L.Kp / kK2EPT) + 255) / 256; break;
-          default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
-        }
-        prefix[(size_t)st * (na + 1) + a] = acc;
-        acc += c;
-      }
-      prefix[(size_t)st * (na + 1) + na] = acc;
-      blocks[st] = acc;
-      if (acc > INT32_MAX) return OZ2_ERR_TOO_LARGE;
-    }
     std::vector<int> order(na);
     for (int a = 0; a < na; ++a) order[a] = a;
     std::stable_sort(order.begin(), order.end(),
@@ -575,7 +583,15 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
           for (int tm = 0; tm < tmn; ++tm)
             items.push_back(WorkItem{(uint16_t)a, (uint16_t)t, (uint16_t)tm, (uint16_t)tn});
     }
+    std::vector<uint16_t> owner((size_t)total_blocks);
+    for (int st = 0; st < kB_NSTAGES; ++st)
+      for (int a = 0; a < na; ++a)
+        for (int64_t bb = prefix[(size_t)st * (na + 1) + a];
+             bb < prefix[(size_t)st * (na + 1) + a + 1]; ++bb)
+          owner[(size_t)(owner_off[st] + bb)] = (uint16_t)a;
     if (hipMemcpyAsync(g_batch.meta + off_prefix, prefix.data(), prefix.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice, g_stream) != hipSuccess ||
+        hipMemcpyAsync(g_batch.meta + off_owner, owner.data(), owner.size() * sizeof(uint16_t),
                        hipMemcpyHostToDevice, g_stream) != hipSuccess ||
         hipMemcpyAsync(g_batch.meta + off_items, items.data(), items.size() * sizeof(WorkItem),
                        hipMemcpyHostToDevice, g_stream) != hipSuccess ||
@@ -584,22 +600,24 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
 
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int64_t gemm_grid = std::min<int64_t>(nitems, (int64_t)cus * 2);
+    // three resident workgroups per CU (32 KiB of LDS, <= 168 VGPRs each)
+    const int64_t gemm_grid = std::min<int64_t>(nitems, (int64_t)cus * 3);
 
-    // Capture: reset counter/status, refresh descriptors, stages, GEMM, CRT.
+    // Capture: reset status, refresh descriptors, stages, GEMM, CRT.
     hipStream_t cs = g_batch.cap;
     BatchProb* d_probs = (BatchProb*)(g_batch.meta + off_probs);
     const int64_t* d_prefix = (const int64_t*)(g_batch.meta + off_prefix);
-    int* d_counter = (int*)(g_batch.meta + off_counter);
     int* d_status = (int*)(g_batch.meta + off_status);
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return OZ2_ERR_HIP;
-    kb_reset<<<1, 64, 0, cs>>>(d_counter, d_status);
+    kb_reset<<<1, 64, 0, cs>>>(d_status);
     (void)hipMemcpyAsync(d_probs, g_batch.h_probs, sizeof(BatchProb) * na, hipMemcpyHostToDevice,
                          cs);
+    const uint16_t* d_owner = (const uint16_t*)(g_batch.meta + off_owner);
 #define OZ2_STAGE(ST)                                                                   \
   if (blocks[ST] > 0)                                                                   \
-    kb_stage<ST><<<(unsigned)blocks[ST], 256, 0, cs>>>(d_probs, d_prefix, na, d_status);
+    kb_stage<ST><<<(unsigned)blocks[ST], 256, 0, cs>>>(d_probs, d_prefix, d_owner + owner_off[ST], \
+                                                       na, d_status);
     OZ2_STAGE(kB_K1A)
     OZ2_STAGE(kB_K1B)
     OZ2_STAGE(kB_FOLDA)
@@ -607,7 +625,7 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
     OZ2_STAGE(kB_K2A)
     OZ2_STAGE(kB_K2B)
     kb_gemm<<<(unsigned)gemm_grid, 256, 0, cs>>>(d_probs, (const WorkItem*)(g_batch.meta + off_items),
-                                                 (int)nitems, d_counter);
+                                                 (int)nitems);
     OZ2_STAGE(kB_K4)
 #undef OZ2_STAGE
     hipError_t e1 = hipStreamEndCapture(cs, &g_batch.graph);
@@ -703,9 +721,9 @@ int ozaki2_get_device_status(int* status) {
   *status = 0;
   if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
   // The status word lives at offset 0 of whichever workspace the last call
-  // used; both candidates are checked and cleared.
-  void* cands[3] = {g_user_ws, g_dev[dev].ws,
-                    g_batch.meta ? (void*)(g_batch.meta + 256) : nullptr};
+  // used (the batch metadata for batched calls); all candidates are checked
+  // and cleared.
+  void* cands[3] = {g_user_ws, g_dev[dev].ws, g_batch.meta ? (void*)g_batch.meta : nullptr};
   for (void* p : cands) {
     if (!p) continue;
     int v = 0;

@@ -73,3 +73,29 @@ def test_batched_argument_errors():
     assert rc == -5 and bad == 1
     rc, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=2)
     assert rc == -3
+
+
+def test_batched_nonfinite_row_sets_status_and_nan_row():
+    """A NaN entry in one problem of a batch: that problem's output row is
+    NaN, everything else is unchanged, and the device status reports the
+    non-finite input once (reading it clears it)."""
+    probs = _problems(4, 6)
+    pairs = [(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)) for A, B, _ in probs]
+    Ns = [N for _, _, N in probs]
+    oz.ozaki2_get_device_status()            # clear whatever earlier calls left
+    clean = [c.cpu().numpy() for c in oz.dgemm_batched(pairs, Ns)]
+    assert oz.ozaki2_get_device_status() == 0
+    bad = 2
+    Abad = pairs[bad][0].clone()
+    Abad[0, 0] = float("nan")
+    pairs2 = list(pairs)
+    pairs2[bad] = (Abad, pairs[bad][1])
+    outs = [c.cpu().numpy() for c in oz.dgemm_batched(pairs2, Ns)]
+    assert oz.ozaki2_get_device_status() == 1   # OZ2_STATUS_NONFINITE
+    assert oz.ozaki2_get_device_status() == 0
+    for i, (C, C0) in enumerate(zip(outs, clean)):
+        if i == bad:
+            assert np.isnan(C[0]).all()
+            assert np.array_equal(_bits(C[1:]), _bits(C0[1:]))
+        else:
+            assert np.array_equal(_bits(C), _bits(C0))
