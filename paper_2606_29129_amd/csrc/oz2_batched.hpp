@@ -37,8 +37,8 @@ struct BatchProb {
 // k slab of the batched GEMM tile (bytes).
 constexpr int kBatchBK = 64;
 
-// The fast modes need at most 3 limbs of 26 bits for |a'| (< 2^78 at N = 20).
-constexpr int kBatchLimbs = 3;
+// The fast modes need at most 2 limbs of 40 bits for |a'| (< 2^79 at N = 20).
+constexpr int kBatchLimbs = 2;
 
 // Stages with a per-problem block count.
 enum BatchStage { kB_K1A = 0, kB_K1B, kB_FOLDA, kB_FOLDB, kB_K2A, kB_K2B, kB_K4, kB_NSTAGES };

@@ -6,12 +6,15 @@
 // the two's-complement low byte for p = 256 (congruent to rmod(a', 256); rmod
 // itself can give +128, which INT8 cannot hold).
 //
-// Residues: a' is split into signed 26-bit limbs, a' = sum_j x_j 2^(26 j)
-// (all limbs carry the sign of a', |x_j| < 2^26), so a' = y (mod p) with
-// y = sum_j x_j (2^(26 j) mod p), |y| < 2^36, exact in binary64.  Then
-// q = rint(y / p) is found from y * RN(1/p) (its error is below 2^-23, far
-// below the 1/(2p) distance of y/p from a half-integer), and r = y - q p is
-// exact: the symmetric residue, with no correction step.
+// Residues: a' is split into signed 40-bit limbs, a' = sum_j x_j 2^(40 j)
+// (all limbs carry the sign of a', |x_j| < 2^40), so a' = y (mod p) with
+// y = sum_j x_j (2^(40 j) mod p).  The fast modes have |a'| < 2^79 (two
+// limbs, |x_1| < 2^39): |y| < 2^40 + 2^47; accurate mode has |a'| < 2^86
+// (three limbs): |y| < 2^40 + 2^48 + 2^14.  So y is exact in binary64, and
+// q = rint(y / p) found from y * RN(1/p) is exact as well: the estimate's
+// error, |y / p| 2^-52 < 2^-3 / p, stays below the 1 / (2p) distance of y / p
+// from a half-integer.  r = y - q p is exact: the symmetric residue, with no
+// correction step.
 //
 // Output layout: plane t is a (Vp x Kp) int8 matrix, vector-major with the
 // k index contiguous (what the GEMM reads); padding rows and columns are 0.
@@ -34,7 +37,7 @@ OZ2_HD Limbs<LIMBS> make_limbs(double a, int32_t e) {
   if (!(v == v)) v = 0.0;  // NaN entries of a flagged row give 0
 #pragma unroll
   for (int j = LIMBS - 1; j >= 1; --j) {
-    const double scale = ldexp(1.0, 26 * j);
+    const double scale = ldexp(1.0, kLimbBits * j);
     double q = trunc(v * (1.0 / scale));
     v = fma(-q, scale, v);
     L.x[j] = q;
@@ -52,9 +55,13 @@ OZ2_HD int residue_odd(const Limbs<LIMBS>& L, const double* pw, double p, double
   return (int)fma(-q, p, y);
 }
 
+// a' = x_0 (mod 256) since 256 divides 2^40; x_0 (|x_0| < 2^40) does not fit
+// an int32, so its low byte is taken exactly in binary64.
 template <int LIMBS>
 OZ2_HD int residue_256(const Limbs<LIMBS>& L) {
-  return (int)(int8_t)(uint8_t)((int32_t)L.x[0] & 0xFF);
+  const double x = L.x[0];
+  const double lo = fma(-256.0, floor(x * (1.0 / 256.0)), x);   // in [0, 256), exact
+  return (int)(int8_t)(uint8_t)(int)lo;
 }
 
 // Residues in plane t of EPT entries (limbs L), packed four to a dword in
@@ -73,7 +80,7 @@ __device__ __forceinline__ void pack_residues(const Limbs<LIMBS> (&L)[EPT], int 
     }
   } else {
     const double p = tab->p[t], ip = tab->inv_p[t];
-    const double* pw = tab->pow26[t];
+    const double* pw = tab->powL[t];
 #pragma unroll
     for (int q = 0; q < EPT / 4; ++q) {
       uint32_t b = 0;

@@ -12,7 +12,7 @@ namespace oz2 {
 constexpr int kMaxN = 20;
 constexpr int kMaxSlices = 4;    // 39-bit slices of P and of the CRT weights
 constexpr int kSliceBits = 39;
-constexpr int kLimbBits = 26;    // limbs of a' used by the residue kernel
+constexpr int kLimbBits = 40;    // limbs of a' used by the residue kernel
 
 // The moduli printed in Section 3.1; N moduli means the first N.
 constexpr int kModuli[kMaxN] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227,
@@ -22,11 +22,11 @@ constexpr int kModuli[kMaxN] = {256, 255, 253, 251, 247, 241, 239, 233, 229, 227
 struct ModTable {
   int N;
   int slices;                      // number of 39-bit slices covering P
-  int limbs;                       // 26-bit limbs covering |a'| (2..4)
+  int limbs;                       // 40-bit limbs covering |a'| (2 or 3)
   int pad_;
   double p[kMaxN];                 // p_t
   double inv_p[kMaxN];             // RN(1/p_t), only for quotient estimates
-  double pow26[kMaxN][4];          // 2^(26 j) mod p_t, j = 0..3
+  double powL[kMaxN][4];           // 2^(40 j) mod p_t, j = 0..3
   double w[kMaxN][kMaxSlices];     // W_t = P_t q_t (< P) in 39-bit slices
   double P[kMaxSlices];            // P in 39-bit slices
   double H[kMaxSlices];            // P/2 in 39-bit slices
@@ -164,7 +164,7 @@ inline bool build_table(int N, bool accurate_limbs, ModTable* T) {
     Big W = Pt.mul_small(q);  // P_t q_t < P, already reduced
     T->p[t] = (double)p;
     T->inv_p[t] = 1.0 / (double)p;
-    for (int j = 0; j < 4; ++j) T->pow26[t][j] = (double)pow2_mod(kLimbBits * j, p);
+    for (int j = 0; j < 4; ++j) T->powL[t][j] = (double)pow2_mod(kLimbBits * j, p);
     for (int s = 0; s < kMaxSlices; ++s) T->w[t][s] = (double)W.bits(kSliceBits * s, kSliceBits);
   }
   uint32_t r2;
