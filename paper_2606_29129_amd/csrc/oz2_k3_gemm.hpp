@@ -196,7 +196,7 @@ __device__ __forceinline__ void gemm_tile(
   // Fragment q (TM blocks of A, then TN blocks of B) of k step kk of LDS
   // buffer buf into register set F.
   v4i fa[2][TM], fb[2][TN];
-  auto fread1 = [&](int buf, int kk, int F, int q) {
+  auto fread_q = [&](int buf, int kk, int F, int q) {
     const int ch = kk * 2 + (lane >> 5);
     if (q < TM) {
       const int8_t* sA = lds[buf] + (wm * (BM / 2)) * BK;
@@ -207,6 +207,11 @@ __device__ __forceinline__ void gemm_tile(
       const int row = (q - TM) * 32 + (lane & 31);
       fb[F][q - TM] = *reinterpret_cast<const v4i*>(sB + row * BK + swz_chunk<BK>(row, ch) * 16);
     }
+  };
+  // The r-th read of a k step: in the order the MFMAs (i-major) consume the
+  // fragments -- A0, B0 .. B(TN-1), then A1 .. A(TM-1).
+  auto fread1 = [&](int buf, int kk, int F, int r) {
+    fread_q(buf, kk, F, r == 0 ? 0 : (r <= TN ? TM + r - 1 : r - TN));
   };
 
   // LX (early-barrier mode only): the first LX loads of slab kt + 2 are
