@@ -17,7 +17,6 @@ the same problem, and the native FP64 DGEMM of the same GPU for context.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -36,9 +35,6 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def load_traffic(m, n, k, N):
@@ -52,7 +48,8 @@ def load_traffic(m, n, k, N):
             key, val = line.split(":", 1)
             kv[key.strip()] = val.strip()
     try:
-        if kv.get("kernel_source_sha256") != _sha(K3_SOURCE):
+        from paper_2606_29129_amd.profiling import source_sha
+        if kv.get("kernel_code_sha256") != source_sha(K3_SOURCE):
             return None
         if kv.get("workload") != f"m={m} n={n} k={k} N={N}":
             return None

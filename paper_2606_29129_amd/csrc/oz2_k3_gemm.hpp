@@ -1,13 +1,14 @@
 // oz2_k3_gemm.hpp -- K3: the N INT8 matrix products of Step 3,
 //   C_t = rmod(A', p_t) rmod(B', p_t)   (INT8 x INT8 -> exact INT32),
-// on gfx950 MFMA (v_mfma_i32_32x32x32_i8), one modulus per grid row.
+// on gfx950 MFMA (v_mfma_i32_32x32x32_i8); all planes and tiles of a call
+// in one 1-D grid.
 //
 // Operands: plane t of RA is Mp x Kp and plane t of RB is Np x Kp, both with
 // the k index contiguous, so C_t = RA_t RB_t^T.  A workgroup of 256 lanes
 // (2 x 2 waves) computes a BM x BN tile; each wave owns (BM/2) x (BN/2) as
-// TM x TN blocks of 32 x 32.  Tiles of BK bytes of k are staged through LDS
+// TM x TN blocks of 32 x 32.  Slabs of BK bytes of k are staged through LDS
 // (double-buffered; 16-byte chunks XOR-swizzled by row so that the 16-byte
-// fragment reads of a 32-row block hit distinct banks) and the next tile's
+// fragment reads of a 32-row block hit distinct banks) and the next slab's
 // global loads are in flight while the current one feeds the MFMAs.
 //
 // Epilogue: |C_t| <= k * 128^2 fits INT32 for k <= 2^17 (Section 2.2).  The
@@ -120,32 +121,33 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 
 // One BM x BN output tile of plane t (tile row tm, tile column tn).
 //
-// Main loop: one 128-byte k slab per iteration, two LDS buffers, four MFMA
-// k steps of 32 bytes per slab.  The instruction order is fixed explicitly
-// (a scheduling fence after every MFMA and the memory operations paired with
-// it), because with one wave per SIMD every stall of the in-order issue is a
-// bubble of the matrix core:
+// Main loop: one BK-byte k slab per iteration (128 bytes for the plain tiles,
+// 64 for the batched one), two LDS buffers, BK / 32 MFMA k steps per slab.
+// The instruction order is fixed explicitly (a scheduling fence after every
+// MFMA and the memory operations paired with it), because with one wave per
+// SIMD every stall of the in-order issue is a bubble of the matrix core:
 //   * in k step kk, the TM + TN fragment reads of step kk + 1 follow the
-//     first TM + TN MFMAs, one after each;
-//   * the next slab's global->LDS loads: half of them ride on MFMAs of the
-//     previous slab's last k step right after its barrier (the buffer they
-//     fill is free from then on), the other half on k steps 0 and 1, so they
-//     have two to four k steps to land (measured 1-4% faster than issuing
-//     all of them in k steps 0 and 1);
-//   * in the last k step, after a few MFMAs, the wave waits for its own
-//     loads and LDS reads and meets the others at the slab barrier; the
-//     next slab is then complete in LDS and the current buffer is free, and
-//     the next slab's step-0 fragment reads follow the remaining MFMAs.
-// So no k step waits for a fragment read issued less than a step earlier,
-// and the barrier sits among MFMAs instead of in front of them.  Lane l of
-// wave w in load round i fills LDS slot 16 (i 256 + 64 w + l); the slot's row
-// and swizzled chunk decide which 16 source bytes it fetches.  The last slab
-// is a separate copy of the body without loads, barrier or read-ahead, so
-// that every slab body is one basic block without conditional loads.
-// EARLY_BARRIER (the default for 256 x 256 tiles) places the slab barrier
-// inside the last k step as described above; smaller tiles, with fewer MFMAs
-// per k step and two workgroups per CU, keep the barrier at the top of the
-// slab and spread the loads over three k steps (measured best for them).
+//     first TM + TN MFMAs, one after each, in the order the i-major MFMAs
+//     consume them;
+//   * EARLY_BARRIER (the default for 256 x 256 tiles): in the last k step,
+//     after a few MFMAs, the wave waits for its own loads and LDS reads and
+//     meets the others at the slab barrier; the next slab is then complete in
+//     LDS and the current buffer is free, and the next slab's step-0 fragment
+//     reads follow the remaining MFMAs.  The next slab's global->LDS loads:
+//     LX = 8 of them ride on MFMAs of the previous slab's last k step right
+//     after its barrier (their buffer is free from then on), the others on
+//     k steps 0 and 1, so they have two to four k steps to land (measured
+//     1-4% faster than issuing all of them in k steps 0 and 1).  So no k step
+//     waits for a fragment read issued less than a step earlier, and the
+//     barrier sits among MFMAs instead of in front of them;
+//   * otherwise (the smaller tiles: fewer MFMAs per k step, two or three
+//     workgroups per CU) the barrier is at the top of the slab and the next
+//     slab's loads are spread over LSTEPS k steps (measured best for them).
+// Lane l of wave w in load round i fills LDS slot 16 (i 256 + 64 w + l); the
+// slot's row and swizzled chunk decide which 16 source bytes it fetches.  The
+// last slabs are separate copies of the body without the loads (and reads
+// ahead) that have no slab to target, so that every slab body is one basic
+// block without conditional loads.
 template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = (BM >= 256 && BN >= 256),
           int LSTEPS = (EARLY_BARRIER ? 2 : 3), int LX = (EARLY_BARRIER ? 8 : 0)>
 __device__ __forceinline__ void gemm_tile(

@@ -23,6 +23,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -33,8 +34,16 @@ COPY_NAME = "AbsFunctor"
 
 
 def source_sha(path: str = K3_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of a C++ source with its comments, leading and
+    trailing blanks and empty lines removed: a profile stays matched to the
+    code it measured when only comments change."""
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.strip() for ln in text.splitlines()]
+    code = "\n".join(ln for ln in lines if ln)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def _find(d: str, suffix: str) -> list[str]:
@@ -126,7 +135,7 @@ def traffic_text(fetch_dir: str, write_dir: str, cmd: str, workload: str, copy_b
         "# HBM traffic of the INT8 GEMM kernel (rocprofv3 --pmc, two passes)",
         f"command: {cmd}",
         f"kernel: {k3f}",
-        f"kernel_source_sha256: {source_sha()}",
+        f"kernel_code_sha256: {source_sha()}",
         f"workload: {workload}",
         f"k3_dispatches_fetch_pass: {fc[k3f]}",
         f"k3_dispatches_write_pass: {wc[k3w]}",

@@ -38,7 +38,7 @@ def test_traffic_scaling(tmp_path):
     assert float(kv["write_scale"]) == pytest.approx(1.0)
     # mean fetch 3000 KiB scaled by 0.5, write 10 KiB
     assert float(kv["hbm_bytes_per_launch"]) == pytest.approx(1500 * 1024 + 10 * 1024)
-    assert kv["kernel_source_sha256"] == profiling.source_sha()
+    assert kv["kernel_code_sha256"] == profiling.source_sha()
 
 
 def test_stats_markdown(tmp_path):
@@ -53,10 +53,21 @@ def test_stats_markdown(tmp_path):
 def test_bench_reads_traffic_file(tmp_path, monkeypatch):
     import bench
     f = tmp_path / "t.txt"
-    f.write_text(f"kernel_source_sha256: {profiling.source_sha()}\n"
+    f.write_text(f"kernel_code_sha256: {profiling.source_sha()}\n"
                  "workload: m=4 n=4 k=4 N=3\nhbm_bytes_per_launch: 1.5e9\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
     assert bench.load_traffic(4, 4, 4, 3) == 1.5e9
     assert bench.load_traffic(4, 4, 4, 4) is None
-    f.write_text("kernel_source_sha256: 0\nworkload: m=4 n=4 k=4 N=3\nhbm_bytes_per_launch: 1\n")
+    f.write_text("kernel_code_sha256: 0\nworkload: m=4 n=4 k=4 N=3\nhbm_bytes_per_launch: 1\n")
     assert bench.load_traffic(4, 4, 4, 3) is None
+
+
+def test_code_hash_ignores_comments_only(tmp_path):
+    a = tmp_path / "a.hpp"
+    a.write_text("int f() {  // one\n  return 1; /* two */\n}\n\n")
+    b = tmp_path / "b.hpp"
+    b.write_text("// header\nint f() {\n    return 1;\n}\n")
+    c = tmp_path / "c.hpp"
+    c.write_text("int f() {\n  return 2;\n}\n")
+    assert profiling.source_sha(str(a)) == profiling.source_sha(str(b))
+    assert profiling.source_sha(str(a)) != profiling.source_sha(str(c))
