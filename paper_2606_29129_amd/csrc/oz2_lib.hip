@@ -27,7 +27,7 @@ __device__ ModTable g_tables[2][kMaxN + 1];
 
 namespace {
 
-constexpr int kBM = 256, kBN = 256, kBK = 128;  // K3 tile
+constexpr int kBM = 256, kBN = 256, kBK = 128;  // largest K3 tile (sizes the workspace)
 constexpr int kMaxDevices = 64;
 
 struct DevState {
@@ -430,7 +430,7 @@ struct BatchState {
   bool launched = false;
   BatchProb* h_probs = nullptr;   // pinned host copy of the descriptors
   size_t h_cap = 0;
-  char* meta = nullptr;           // device: counter, status, descriptors, prefixes, items
+  char* meta = nullptr;           // device: status, descriptors, prefixes, items, owners
   size_t meta_bytes = 0;
 };
 BatchState g_batch;
@@ -749,7 +749,8 @@ const char* ozaki2_status_string(int code) {
 }
 
 const char* ozaki2_version(void) {
-  return "ozaki2 0.1 gfx950 kc=64 slice=39 limb=26 log2=rn32(log2_f64) tile=256x256x128";
+  return "ozaki2 0.2 gfx950 kc=64 slice=39 limb=40 log2=rn32(log2_f64) "
+         "tiles=256x256x128,128x128x128,256x64x128(auto) batched=128x128x64";
 }
 
 int ozaki2_finalize(void) {
