@@ -4,6 +4,7 @@
     python -m paper_2606_29129_amd.sweep shapes
     python -m paper_2606_29129_amd.sweep scale
     python -m paper_2606_29129_amd.sweep accuracy [--block 512]
+    python -m paper_2606_29129_amd.sweep sgemm [--sizes 4096,8192,16384]
 
 Every result is one JSON line on stdout.
 
@@ -24,6 +25,9 @@ Every result is one JSON line on stdout.
   componentwise error on a block of rows and columns picked by a seeded
   permutation, against a double-double product over the full k; the
   fraction of zero entries of A' and B' (a' = trunc(a 2^e)).
+
+* ``sgemm``: binary32 emulation (Section 5) over sizes for N = 5..9 beside
+  native binary32 ``torch.matmul``.
 
 Errors: ``max_rel`` = max |C - R| / |R| over R != 0 (``zero_ref_nonzero``
 counts R = 0 with C != 0), ``max_cw`` = max |C - R| / (|A||B|)_ij.  The
@@ -236,6 +240,36 @@ def sweep_throughput(args):
             torch.cuda.empty_cache()
 
 
+def sweep_sgemm(args):
+    """SGEMM emulation (binary32 in and out, Section 5): throughput for
+    N = 5..9 beside native binary32 torch.matmul, error on a sampled block
+    against a double-double product of the binary32 inputs."""
+    import torch
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(3)
+    for S in [int(x) for x in args.sizes.split(",")]:
+        A = inputs.ozaki_matrix_torch(S, S, 1.0, 0, 0, dev).float()
+        B = inputs.ozaki_matrix_torch(S, S, 1.0, 0, 1, dev).float()
+        native, _ = _native_ms(torch, A, B)
+        rows = np.sort(rng.choice(S, args.sample, replace=False))
+        cols = np.sort(rng.choice(S, args.sample, replace=False))
+        Ah = A[torch.as_tensor(rows, device=dev)].double().cpu().numpy()
+        Bh = B[:, torch.as_tensor(cols, device=dev)].double().cpu().numpy()
+        ref, absAB = _block(Ah, Bh, rows, cols)
+        P = Problem(torch, A, B, 9, single=True)
+        for N in range(5, 10):
+            ms, st = _timed(torch, lambda: P.run(N), args.steps, args.warmup)
+            flops = 2.0 * S ** 3
+            _emit(dict(leg="sgemm", m=S, n=S, k=S, phi=1.0, N=N, ms=round(ms, 4),
+                       tflops=round(flops / ms / 1e9, 2), stage_ms=st,
+                       native_fp32_tflops=round(flops / native / 1e9, 2),
+                       sample=f"{args.sample}x{args.sample} block",
+                       **errors(P.C_block(rows, cols), ref, absAB)))
+        P.release()
+        del A, B
+        torch.cuda.empty_cache()
+
+
 def sweep_shapes(args):
     import torch
     dev = torch.device("cuda:0")
@@ -355,7 +389,7 @@ def sweep_accuracy(args):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy"])
+    ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy", "sgemm"])
     ap.add_argument("--sizes", default="1024,4096,8192,16384")
     ap.add_argument("--phis", default="0.5,1,2,4")
     ap.add_argument("--Ns", default="12,14,16,18,20")
@@ -367,7 +401,7 @@ def main(argv=None):
     ap.add_argument("--scale-size", type=int, default=4096)
     a = ap.parse_args(argv)
     {"throughput": sweep_throughput, "shapes": sweep_shapes, "scale": sweep_scale,
-     "accuracy": sweep_accuracy}[a.leg](a)
+     "accuracy": sweep_accuracy, "sgemm": sweep_sgemm}[a.leg](a)
 
 
 if __name__ == "__main__":

@@ -306,3 +306,22 @@ def test_every_tile_shape_gives_the_same_bits(tile, mode):
         assert _bits_equal(_gpu_dgemm(A, B, N, mode=mode), r["C"])
     finally:
         oz.ozaki2_set_tile(0)
+
+
+def test_too_small_caller_workspace_falls_back_to_library_memory():
+    """ozaki2_set_workspace with fewer bytes than a call needs: the call uses
+    library-owned memory instead and the result is unchanged; a large enough
+    caller workspace is used as is."""
+    A, B = inputs.problem(130, 90, 150, 1.0, seed=11)
+    want = ref.dgemm(A, B, 14)
+    need = oz.ozaki2_workspace_size(130, 90, 150, 14, 0)
+    small = torch.empty(need // 4, dtype=torch.uint8, device=DEV)
+    big = torch.empty(need + 256, dtype=torch.uint8, device=DEV)
+    try:
+        assert oz.ozaki2_set_workspace((small.data_ptr() + 255) // 256 * 256, need // 8) == 0
+        assert _bits_equal(_gpu_dgemm(A, B, 14), want)
+        assert oz.ozaki2_set_workspace((big.data_ptr() + 255) // 256 * 256, need) == 0
+        assert _bits_equal(_gpu_dgemm(A, B, 14), want)
+        assert oz.ozaki2_set_workspace(big.data_ptr() + 8, need) == -1   # misaligned
+    finally:
+        oz.ozaki2_set_workspace(None, 0)
