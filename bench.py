@@ -13,6 +13,11 @@ with phi = 0.5 and seed 0 (the distribution of the paper's experiments), N =
 the dominant kernel (the INT8 GEMM, timed with HIP events on the library's
 stream during the timed steps), the CPU oracle timed on a bounded sample of
 the same problem, and the native FP64 DGEMM of the same GPU for context.
+Two more legs fill fields of the same line: ``fixed_error`` times the same
+product with N picked by the autotuner for a max relative error target
+(default 1e-15, measured on sampled entries against exact values), and
+``batched`` times 256 uneven problems (N per problem for the same target) in
+one graph launch against one call per problem.
 """
 from __future__ import annotations
 
@@ -99,6 +104,48 @@ def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0):
                 seconds=round(elapsed, 2)), done, exact_ok, max_rel
 
 
+def fixed_error_leg(A_rm, B_rm, A_cm, B_cm, m, n, k, mode, target, stream, seed,
+                    steps=3, samples=16):
+    """The same product with N picked by the autotuner for the max relative
+    error target (phi estimated from the data); its error is measured on
+    sampled entries against their exact values."""
+    import numpy as np
+    import torch
+    from paper_2606_29129_amd import autotune
+    from paper_2606_29129_amd import ozaki2 as oz
+
+    phi_hat = max(autotune.estimate_phi(A_rm), autotune.estimate_phi(B_rm))
+    Nt = autotune.pick_N(k, phi_hat, target)
+    C_cm = torch.empty((n, m), dtype=torch.float64, device=A_cm.device)  # its own output
+
+    def step():
+        rc = oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, Nt, mode)
+        if rc:
+            raise oz.Ozaki2Error("ozaki2_dgemm", rc)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rng = np.random.default_rng(seed + 99)
+    worst = 0.0
+    for _ in range(samples):
+        i, j = int(rng.integers(m)), int(rng.integers(n))
+        ref = autotune.exact_dot(A_rm[i].cpu().numpy(), B_rm[:, j].cpu().numpy())
+        worst = max(worst, autotune.rel_err(float(C_cm[j, i]), ref))
+    del C_cm
+    torch.cuda.empty_cache()
+    return dict(target_max_rel_err=target, phi_estimated=round(phi_hat, 3), N=Nt,
+                ms_per_step=round(ms, 4), tflops=round(2.0 * m * n * k / (ms * 1e-3) / 1e12, 2),
+                sampled_entries=samples, max_rel_err_sampled=worst,
+                note="N from the autotuner's calibrated table for the target")
+
+
 def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
     """256 independent DGEMMs, m, n, k log-uniform in [64, 2048], phi uniform
     in [0.5, 3], N per problem from the autotuner for the target max relative
@@ -182,6 +229,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fixed-error", action="store_true",
+                    help="skip the leg with N picked by the autotuner for --target")
+    ap.add_argument("--target", type=float, default=1e-15,
+                    help="max relative error target of the fixed-error and batched legs")
     ap.add_argument("--traffic-calibration", type=int, default=0, metavar="BYTES",
                     help="before the steps, run one torch.abs over a float64 tensor of "
                          "BYTES bytes (the known-size kernel that scales rocprofv3 "
@@ -272,6 +323,13 @@ def main():
     _log(f"stages ms/call: {st}; K3 {achieved:.0f} TOP/s = "
          f"{100 * achieved / INT8_PEAK_TOPS:.1f}% of INT8 peak")
 
+    fixed = None
+    if not args.no_fixed_error and mode != 2:
+        fixed = fixed_error_leg(A_rm, B_rm, A_cm, B_cm, m, n, k, mode, args.target,
+                                stream, args.seed)
+        _log(f"fixed error {args.target:g}: N={fixed['N']} -> {fixed['tflops']} TFLOPS, "
+             f"max rel err on {fixed['sampled_entries']} entries {fixed['max_rel_err_sampled']:.2e}")
+
     native = None
     if not args.no_native:
         Cn = torch.matmul(A_rm, B_rm)
@@ -298,7 +356,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_leg(args.steps, args.warmup)
+        batched = batched_leg(args.steps, args.warmup, target=args.target)
         _log(f"batched: {batched['tflops_batched']} TFLOPS in one graph launch vs "
              f"{batched['tflops_plain']} TFLOPS plain ({batched['speedup']}x), "
              f"N {batched['N_histogram']}, max rel err {batched['max_rel_err_sampled']:.2e}")
@@ -330,6 +388,7 @@ def main():
         "stage_ms_per_step": st,
         "native_fp64_tflops": None if native is None else round(native, 2),
         "sample_check": sample_check,
+        "fixed_error": fixed,
         "batched": batched,
         "context": {"paper_gh200_cublas_dgemm_tflops": 60.9,
                     "paper_gh200_ozaki2_dgemm_tflops_up_to": 80.2},

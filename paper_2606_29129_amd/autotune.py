@@ -42,8 +42,8 @@ TILE_SHAPES = ((1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096), (8192
                (32768, 128, 4096), (16384, 256, 2048), (512, 512, 4096), (3000, 3000, 3000),
                (16384, 16384, 16384))
 
-K_GRID = (64, 256, 1024, 2048)
-PHI_GRID = (0.5, 1.0, 1.5, 2.0, 2.5, 3.0)
+K_GRID = (64, 256, 1024, 2048, 8192, 16384)
+PHI_GRID = (0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.0)
 N_GRID = tuple(range(10, 21))
 
 
