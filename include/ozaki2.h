@@ -46,8 +46,9 @@ extern "C" {
 
 /* Status codes (positive; argument errors are negative). */
 #define OZ2_SUCCESS          0
-#define OZ2_ERR_K_TOO_LARGE  1 /* k > 2^17: INT32 accumulation could overflow
-                                  (Section 2.2); blocking is not implemented */
+#define OZ2_ERR_K_TOO_LARGE  1 /* k above OZ2_K_MAX (OZ2_K_MAX_ACCURATE in
+                                  accurate mode, OZ2_K_BLOCK per problem of a
+                                  batch) */
 #define OZ2_ERR_WORKSPACE    2 /* workspace allocation failed */
 #define OZ2_ERR_HIP          3 /* a HIP runtime call failed */
 #define OZ2_ERR_UNSUPPORTED  4 /* valid request this build does not support */
@@ -61,13 +62,22 @@ extern "C" {
 /* Limits. */
 #define OZ2_N_MIN 2
 #define OZ2_N_MAX 20
-#define OZ2_K_MAX 131072 /* 2^17 */
+#define OZ2_K_BLOCK 131072        /* 2^17: k per INT8 GEMM launch; the INT32
+                                     products of one block are exact
+                                     (|C_t| <= 2^17 * 127^2 < 2^31; Section 2.2
+                                     requires exact products), larger k is
+                                     summed over blocks modulo p_t */
+#define OZ2_K_MAX 4194304         /* 2^22 (grid limits of the norm and
+                                     split kernels) */
+#define OZ2_K_MAX_ACCURATE 262144 /* 2^18: accurate mode's bar product (entries
+                                     <= 64^2 k) stays exact in INT32 */
 
 /*
  * ozaki2_dgemm -- C ~ A B for binary64 A (m x k, lda) and B (k x n, ldb);
  * C (m x n, ldc) is binary64.
  *
- *   m, n, k   >= 0 (args 1-3); k <= OZ2_K_MAX.
+ *   m, n, k   >= 0 (args 1-3); k <= OZ2_K_MAX (OZ2_K_MAX_ACCURATE in
+ *             accurate mode).
  *   A, lda    device pointer, lda >= max(1, m) (args 4-5).
  *   B, ldb    device pointer, ldb >= max(1, k) (args 6-7).
  *   C, ldc    device pointer, ldc >= max(1, m) (args 8-9).
@@ -197,8 +207,8 @@ typedef struct oz2_problem {
  *
  * All problems are computed by one HIP graph launch: the stages of
  * ozaki2_dgemm run once for the whole batch (one grid per stage) and the
- * INT8 GEMMs of every problem and modulus run in one persistent kernel that
- * takes tiles from a shared work list.  The graph is built on the first call
+ * INT8 GEMMs of every problem and modulus run in one persistent kernel over
+ * a shared work list.  k <= OZ2_K_BLOCK per problem.  The graph is built on the first call
  * with a given batch signature (shapes, N, mode, workspace) and replayed
  * afterwards; only the matrix pointers are refreshed per call (a small host
  * -> device copy inside the graph).  Results are bit-identical to calling
@@ -221,7 +231,8 @@ int ozaki2_dgemm_batched(int batch, const oz2_problem* problems, int mode,
  *   RA[N*m*k]         int8 residues of A': element (t, i, h) at t*m*k + i*k + h
  *   RB[N*n*k]         int8 residues of B': element (t, j, h) at t*n*k + j*k + h
  *   Ct[m*n]           int32 product rmod(A',p_t) rmod(B',p_t) for modulus
- *                     index t (0-based), column-major (i + j*m)
+ *                     index t (0-based), column-major (i + j*m); only for
+ *                     k <= OZ2_K_BLOCK (else OZ2_ERR_UNSUPPORTED)
  * Test hook for stage-by-stage comparison with a reference.  Synchronises
  * the stream before returning.
  */

@@ -20,7 +20,9 @@
 // Other epilogues (EPI): 1 stores the raw INT32 product of one plane (test
 // hook); 2 (accurate mode's scale GEMM on the bar planes, Section 2.3) does
 // not store the product at all: it folds it into row and column maxima with
-// integer atomicMax (entries are >= 0, and the maxima start at 0).
+// integer atomicMax (entries are >= 0, and the maxima start at 0); 3 is EPI 0
+// for a later block of k (k > 2^17 is split into blocks whose INT32 products
+// are exact): U_t = (U_t + C_t mod p_t) mod p_t.
 #pragma once
 
 #include <type_traits>
@@ -155,7 +157,7 @@ __device__ __forceinline__ void gemm_tile(
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
     const ModTable* __restrict__ tab, int t, int tm, int tn,
-    int8_t (*__restrict__ lds)[(BM + BN) * BK]) {
+    int8_t (*__restrict__ lds)[(BM + BN) * BK], int64_t k0 = 0, int64_t klen = -1) {
   constexpr int TM = BM / 64, TN = BN / 64;      // 32x32 blocks per wave
   constexpr int CH = BK / 16;                    // 16-byte chunks per row
   constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
@@ -165,8 +167,10 @@ __device__ __forceinline__ void gemm_tile(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const int8_t* gA = RA + (int64_t)t * Mp * Kp + (int64_t)tm * BM * Kp;
-  const int8_t* gB = RB + (int64_t)t * Np * Kp + (int64_t)tn * BN * Kp;
+  // k columns [k0, k0 + klen) of the planes (rows of Kp bytes); klen < 0: all
+  const int8_t* gA = RA + (int64_t)t * Mp * Kp + (int64_t)tm * BM * Kp + k0;
+  const int8_t* gB = RB + (int64_t)t * Np * Kp + (int64_t)tn * BN * Kp + k0;
+  if (klen < 0) klen = Kp;
 
   v16i acc[TM][TN];
 #pragma unroll
@@ -231,7 +235,7 @@ __device__ __forceinline__ void gemm_tile(
   static_assert(SP >= 1 && PER * LSTEPS >= LY, "loads fit the MFMA slots");
   static_assert(LX == 0 || (EARLY_BARRIER && LX <= NM - BAR - 1 && LX <= 63), "early loads");
 
-  const int nk = (int)(Kp / BK);
+  const int nk = (int)(klen / BK);
 #pragma unroll
   for (int i = 0; i < LOADS; ++i) gload1(0, 0, i);
   if constexpr (EARLY_BARRIER) {
@@ -377,6 +381,23 @@ __device__ __forceinline__ void gemm_tile(
       const int64_t bi = (int64_t)tm * (BM / 32) + wm * (TM) + i;
       const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;
       uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
+      if constexpr (EPI == 3) {
+        // a later k block: U = (U + C mod p) mod p, byte by byte
+        const uint4 o = *reinterpret_cast<const uint4*>(dst);
+        const uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t pu = (uint32_t)p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t b = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            uint32_t v = ((ow[q] >> (8 * e)) & 0xFFu) + ((w[q] >> (8 * e)) & 0xFFu);
+            v = is256 ? (v & 0xFFu) : (v >= pu ? v - pu : v);
+            b |= v << (8 * e);
+          }
+          w[q] = b;
+        }
+      }
       *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
@@ -386,13 +407,14 @@ __global__ __launch_bounds__(256) void k3_gemm_i8(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
-    const ModTable* __restrict__ tab, int t_raw) {
+    const ModTable* __restrict__ tab, int t_raw, int64_t k0, int64_t klen) {
   __shared__ __attribute__((aligned(16))) int8_t lds[2][(BM + BN) * BK];
   const int tiles_m = (int)(Mp / BM), tiles_n = (int)(Np / BN);
   int plane, tm, tn;
   tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, &plane, &tm, &tn);
-  const int t = EPI != 0 ? t_raw : plane;
-  gemm_tile<BM, BN, BK, EPI>(RA, RB, U, aux0, aux1, m, n, Mp, Np, Kp, tab, t, tm, tn, lds);
+  const int t = (EPI == 1 || EPI == 2) ? t_raw : plane;
+  gemm_tile<BM, BN, BK, EPI>(RA, RB, U, aux0, aux1, m, n, Mp, Np, Kp, tab, t, tm, tn, lds, k0,
+                             klen);
 }
 
 }  // namespace oz2

@@ -155,7 +155,8 @@ int check_args(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
   if (N < OZ2_N_MIN || N > OZ2_N_MAX) return -10;
   if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL && mode != OZ2_MODE_ACCURATE)
     return -11;
-  if (k > OZ2_K_MAX) return OZ2_ERR_K_TOO_LARGE;
+  if (k > OZ2_K_MAX || (mode == OZ2_MODE_ACCURATE && k > OZ2_K_MAX_ACCURATE))
+    return OZ2_ERR_K_TOO_LARGE;
   if (m > (int64_t)INT32_MAX / 2 || n > (int64_t)INT32_MAX / 2) return OZ2_ERR_TOO_LARGE;
   return 0;
 }
@@ -258,22 +259,34 @@ void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, i
 template <int EPI>
 void launch_gemm(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* U, int32_t* aux0,
                  int32_t* aux1, int64_t m, int64_t n, const Layout& L, const ModTable* tab,
-                 int t, int planes) {
+                 int t, int planes, int64_t k0 = 0, int64_t klen = -1) {
   const unsigned tiles =
       (unsigned)((L.Mp / kTileBM[cfg]) * (L.Np / kTileBN[cfg]) * planes);
+  if (klen < 0) klen = L.Kp;
   switch (cfg) {
     case OZ2_TILE_128x128:
-      k3_gemm_i8<128, 128, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
-                                                                 L.Mp, L.Np, L.Kp, tab, t);
+      k3_gemm_i8<128, 128, kBK, EPI><<<tiles, 256, 0, g_stream>>>(
+          RA, RB, U, aux0, aux1, m, n, L.Mp, L.Np, L.Kp, tab, t, k0, klen);
       break;
     case OZ2_TILE_256x64:
-      k3_gemm_i8<256, 64, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
-                                                                L.Mp, L.Np, L.Kp, tab, t);
+      k3_gemm_i8<256, 64, kBK, EPI><<<tiles, 256, 0, g_stream>>>(
+          RA, RB, U, aux0, aux1, m, n, L.Mp, L.Np, L.Kp, tab, t, k0, klen);
       break;
     default:
-      k3_gemm_i8<256, 256, kBK, EPI><<<tiles, 256, 0, g_stream>>>(RA, RB, U, aux0, aux1, m, n,
-                                                                 L.Mp, L.Np, L.Kp, tab, t);
+      k3_gemm_i8<256, 256, kBK, EPI><<<tiles, 256, 0, g_stream>>>(
+          RA, RB, U, aux0, aux1, m, n, L.Mp, L.Np, L.Kp, tab, t, k0, klen);
       break;
+  }
+}
+
+// K3 over all N planes; k beyond OZ2_K_BLOCK in blocks of OZ2_K_BLOCK (each
+// block's INT32 products are exact; later blocks add theirs modulo p_t).
+void launch_gemm_blocked(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* U, int64_t m,
+                         int64_t n, const Layout& L, const ModTable* tab, int N) {
+  for (int64_t k0 = 0; k0 < L.Kp; k0 += OZ2_K_BLOCK) {
+    const int64_t klen = std::min<int64_t>(OZ2_K_BLOCK, L.Kp - k0);
+    if (k0 == 0) launch_gemm<0>(cfg, RA, RB, U, nullptr, nullptr, m, n, L, tab, 0, N, k0, klen);
+    else launch_gemm<3>(cfg, RA, RB, U, nullptr, nullptr, m, n, L, tab, 0, N, k0, klen);
   }
 }
 
@@ -292,6 +305,7 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, N, mode, dbg == nullptr);
   if (rc) return rc;
   if (dbg && (dbg->t < 0 || dbg->t >= N)) return -10;
+  if (dbg && dbg->Ct && k > OZ2_K_BLOCK) return OZ2_ERR_UNSUPPORTED;  // INT32 of one block
   if (m == 0 || n == 0) return 0;
   int dev;
   if ((rc = ensure_device(&dev))) return rc;
@@ -378,8 +392,8 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
       launch_gemm<1>(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr,
                      dbg->Ct, nullptr, m, n, L, tab, dbg->t, 1);
   } else {
-    launch_gemm<0>(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB),
-                   (uint8_t*)(ws + L.U), nullptr, nullptr, m, n, L, tab, 0, N);
+    launch_gemm_blocked(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB),
+                        (uint8_t*)(ws + L.U), m, n, L, tab, N);
   }
   clk.mark(3);
   // K4: CRT and unscaling.
@@ -458,6 +472,7 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
     const oz2_problem& q = P[i];
     int rc = check_args(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, q.N, mode, true);
     if (!rc && q.reserved != 0) rc = -12;
+    if (!rc && q.k > OZ2_K_BLOCK) rc = OZ2_ERR_K_TOO_LARGE;  // no k blocking in a batch
     if (!rc && (q.m > 65535 * (int64_t)kBatchTile || q.n > 65535 * (int64_t)kBatchTile))
       rc = OZ2_ERR_TOO_LARGE;
     if (rc) {
@@ -739,7 +754,8 @@ const char* ozaki2_status_string(int code) {
   if (code < 0) return "invalid argument (the negated return value is its 1-based position)";
   switch (code) {
     case OZ2_SUCCESS: return "success";
-    case OZ2_ERR_K_TOO_LARGE: return "k exceeds 2^17 (INT32 accumulation limit)";
+    case OZ2_ERR_K_TOO_LARGE:
+      return "k exceeds the limit (2^22; 2^18 in accurate mode; 2^17 per problem of a batch)";
     case OZ2_ERR_WORKSPACE: return "workspace allocation failed";
     case OZ2_ERR_HIP: return "HIP runtime error";
     case OZ2_ERR_UNSUPPORTED: return "unsupported request";

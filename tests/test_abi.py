@@ -44,7 +44,8 @@ def test_library_exports_every_declared_symbol():
     ((4, 4, 4, 1, 4, 1, 4, 1, 4, 1, 0), -10),
     ((4, 4, 4, 1, 4, 1, 4, 1, 4, 21, 0), -10),
     ((4, 4, 4, 1, 4, 1, 4, 1, 4, 14, 3), -11),
-    ((4, 4, 2**17 + 1, 1, 4, 1, 2**17 + 1, 1, 4, 14, 0), 1),
+    ((4, 4, 2**22 + 1, 1, 4, 1, 2**22 + 1, 1, 4, 14, 0), 1),    # OZ2_K_MAX
+    ((4, 4, 2**18 + 1, 1, 4, 1, 2**18 + 1, 1, 4, 14, 2), 1),    # accurate mode
 ])
 def test_argument_errors_are_reported_without_device_work(args, code):
     assert oz.ozaki2_dgemm(*args) == code
@@ -103,3 +104,17 @@ def test_tile_policy_and_automatic_choice():
     assert lib.ozaki2_get_tile(1, 1, 1, 1, ctypes.byref(t)) == -4
     assert lib.ozaki2_get_tile(-1, 1, 1, 14, ctypes.byref(t)) == -1
     assert lib.ozaki2_get_tile(1, 1, 1, 14, None) == -5
+
+
+def test_k_limits_of_the_header():
+    """The k limits: one INT8 GEMM block, the general limit, accurate mode's;
+    a batch rejects k beyond one block for its problem."""
+    hdr = open(os.path.join(ROOT, "include", "ozaki2.h")).read()
+    vals = {k: int(v) for k, v in re.findall(r"#define (OZ2_K_\w+)\s+(\d+)", hdr)}
+    assert vals == {"OZ2_K_BLOCK": 2**17, "OZ2_K_MAX": 2**22, "OZ2_K_MAX_ACCURATE": 2**18}
+    # INT32 exactness of one block for odd moduli, and of the bar product
+    assert 2**17 * 127**2 < 2**31 and 64 * 64 * 2**18 < 2**31
+    bad = ctypes.c_int(-1)
+    prob = oz.Oz2Problem(4, 4, 2**17 + 1, 8, 4, 8, 2**17 + 1, 8, 4, 14, 0)
+    arr = (oz.Oz2Problem * 1)(prob)
+    assert oz.lib().ozaki2_dgemm_batched(1, arr, 0, ctypes.byref(bad)) == 1 and bad.value == 0

@@ -325,3 +325,21 @@ def test_too_small_caller_workspace_falls_back_to_library_memory():
         assert oz.ozaki2_set_workspace(big.data_ptr() + 8, need) == -1   # misaligned
     finally:
         oz.ozaki2_set_workspace(None, 0)
+
+
+@pytest.mark.parametrize("m,n,k,N,mode", [(6, 5, 2**17 + 5000, 14, 0), (3, 4, 2**18 + 77, 20, 1)])
+def test_k_beyond_one_int32_block(m, n, k, N, mode):
+    """k > 2^17 runs the INT8 GEMMs over k blocks of 2^17 (each block's INT32
+    products exact) and sums the blocks modulo p_t: C equals the oracle's,
+    which forms each C_t over the whole k in int64."""
+    print(f"case m={m} n={n} k={k} N={N} mode={mode}", flush=True)
+    A, B = inputs.problem(m, n, k, 1.0, seed=23 + mode)
+    r = ref.gemm(A, B, N, (ref.REVISED, ref.ORIGINAL)[mode])
+    assert _bits_equal(_gpu_dgemm(A, B, N, mode=mode), r["C"])
+    # the INT32 debug product exists only for one block
+    Ad, lda = _colmajor(A)
+    Bd, ldb = _colmajor(B)
+    Ct = torch.zeros(m * n, dtype=torch.int32, device=DEV)
+    rc = oz.ozaki2_debug_stages(m, n, k, Ad, lda, Bd, ldb, N, mode, 0,
+                                None, None, None, None, None, None, Ct)
+    assert rc == 4   # OZ2_ERR_UNSUPPORTED
