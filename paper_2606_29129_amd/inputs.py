@@ -12,7 +12,8 @@ stream so that any entry can be regenerated from (seed, stream, index):
 ``mix64`` is the finaliser of Vigna's public-domain SplitMix64 generator.
 randn uses the Box-Muller transform on two further streams.  Matrix A uses
 streams 0, 1, 2 and matrix B streams 3, 4, 5 (rand, Box-Muller u1, u2); the
-entry (r, c) of an R x C matrix has index r * C + c.
+imaginary parts of complex A and B use streams 6-8 and 9-11; the entry (r, c)
+of an R x C matrix has index r * C + c.
 
 ``ozaki_matrix_torch`` evaluates the same streams with torch integer ops on
 any device (integer arithmetic wraps modulo 2**64 exactly as in numpy, so the
@@ -79,6 +80,15 @@ def problem(m: int, n: int, k: int, phi: float, seed: int = 0):
     return ozaki_matrix(m, k, phi, seed, 0), ozaki_matrix(k, n, phi, seed, 1)
 
 
+def complex_problem(m: int, n: int, k: int, phi: float, seed: int = 0):
+    """(A, B) complex128 for C = A B: real and imaginary parts drawn
+    independently from the distribution above (A: streams 0-2 real, 6-8
+    imaginary; B: streams 3-5 real, 9-11 imaginary)."""
+    A = ozaki_matrix(m, k, phi, seed, 0) + 1j * ozaki_matrix(m, k, phi, seed, 2)
+    B = ozaki_matrix(k, n, phi, seed, 1) + 1j * ozaki_matrix(k, n, phi, seed, 3)
+    return A, B
+
+
 def ones_problem(m: int, n: int, k: int, s: int):
     """A = 2**s J (m x k) and B = 2**s J (k x n), the all-ones case of
     Section 3.1."""
@@ -129,3 +139,13 @@ def ozaki_matrix_torch(rows: int, cols: int, phi: float, seed: int = 0, which: i
         z = torch.sqrt(-2.0 * torch.log1p(-u1)) * torch.cos(2.0 * torch.pi * u2)
         out[s:s + c] = (r - 0.5) * torch.exp(phi * z)
     return out.view(rows, cols)
+
+
+def complex_matrix_torch(rows: int, cols: int, phi: float, seed: int = 0, which: int = 0,
+                         device="cuda"):
+    """Complex counterpart of ``ozaki_matrix_torch`` (``complex_problem``'s
+    streams: which = 0 for A, 1 for B) as a row-major complex128 tensor."""
+    import torch
+    re = ozaki_matrix_torch(rows, cols, phi, seed, which, device)
+    im = ozaki_matrix_torch(rows, cols, phi, seed, which + 2, device)
+    return torch.complex(re, im)

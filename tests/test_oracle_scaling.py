@@ -1,10 +1,7 @@
 """Pins for the oracle's scale exponents (CPU only)."""
-import ctypes
 import math
 import os
 import random
-import subprocess
-import tempfile
 from fractions import Fraction
 
 import numpy as np
@@ -14,18 +11,6 @@ from oracle import constants, fp, scaling
 from paper_2606_29129_amd import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-
-
-@pytest.fixture(scope="module")
-def fenv():
-    d = tempfile.mkdtemp()
-    so = os.path.join(d, "fenv_ref.so")
-    subprocess.check_call(["gcc", "-O0", "-frounding-math", "-shared", "-fPIC",
-                           os.path.join(HERE, "fenv_ref.c"), "-o", so, "-lm"])
-    lib = ctypes.CDLL(so)
-    lib.ru_norm_chunked.restype = ctypes.c_double
-    lib.ru_norm_chunked.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]
-    return lib
 
 
 def test_norm_matches_fpu_upward_rounding(fenv):
