@@ -17,7 +17,8 @@ Two more legs fill fields of the same line: ``fixed_error`` times the same
 product with N picked by the autotuner for a max relative error target
 (default 1e-15, measured on sampled entries against exact values), and
 ``batched`` times 256 uneven problems (N per problem for the same target) in
-one graph launch against one call per problem.
+one graph launch against one call per problem; ``complex`` times ZGEMM at
+8192^3 (three INT8 GEMMs per modulus) beside native complex128 matmul.
 """
 from __future__ import annotations
 
@@ -212,6 +213,90 @@ def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
                 sampled="16 entries of each of %d problems vs the exact product" % check)
 
 
+def complex_leg(size, N, phi, seed, steps, warmup, samples=8):
+    """ZGEMM m = n = k = size on complex128 inputs whose real and imaginary
+    parts follow the same distribution: 8mnk/t, per-stage times, the INT8
+    rate of its 3N GEMMs, native complex128 torch.matmul of the same GPU, and
+    the normwise error |c - r| / |r| of sampled entries against their exact
+    values."""
+    import math
+    from fractions import Fraction
+    import numpy as np
+    import torch
+    from paper_2606_29129_amd import autotune, inputs
+    from paper_2606_29129_amd import ozaki2 as oz
+
+    dev = torch.device("cuda:0")
+    A = inputs.complex_matrix_torch(size, size, phi, seed, 0, dev)
+    B = inputs.complex_matrix_torch(size, size, phi, seed, 1, dev)
+    A_cm, B_cm = A.t().contiguous(), B.t().contiguous()
+    C_cm = torch.empty((size, size), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc = oz.ozaki2_zgemm(size, size, size, A_cm, size, B_cm, size, C_cm, size, N, 0)
+        if rc:
+            raise oz.Ozaki2Error("ozaki2_zgemm", rc)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    oz._check("ozaki2_set_timing", oz.ozaki2_set_timing(1))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stage_ms, calls = oz.ozaki2_get_stage_times()
+    oz.ozaki2_set_timing(0)
+    ms = e0.elapsed_time(e1) / steps
+    st = {name: round(v / max(calls, 1), 4) for name, v in zip(oz.STAGE_NAMES, stage_ms)}
+    k3_ms = stage_ms[2] / max(calls, 1)
+    k3_ops = 6.0 * N * size ** 3
+    flops = 8.0 * size ** 3
+
+    Cn = torch.matmul(A, B)
+    torch.cuda.synchronize()
+    reps = 2
+    e0.record(stream)
+    for _ in range(reps):
+        torch.matmul(A, B, out=Cn)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    native = flops / (e0.elapsed_time(e1) / reps * 1e-3) / 1e12
+    del Cn
+
+    def frac(v):
+        n, e = v
+        return Fraction(n) * Fraction(2) ** e
+
+    rng = np.random.default_rng(seed + 7)
+    worst = 0.0
+    for _ in range(samples):
+        i, j = int(rng.integers(size)), int(rng.integers(size))
+        a, b = A[i].cpu().numpy(), B[:, j].cpu().numpy()
+        Rr = frac(autotune.exact_dot(np.concatenate([a.real, -a.imag]),
+                                     np.concatenate([b.real, b.imag])))
+        Ri = frac(autotune.exact_dot(np.concatenate([a.real, a.imag]),
+                                     np.concatenate([b.imag, b.real])))
+        c = complex(C_cm[j, i].item())
+        dr, di = Fraction(c.real) - Rr, Fraction(c.imag) - Ri
+        den = Rr * Rr + Ri * Ri
+        if den:
+            worst = max(worst, math.sqrt(float((dr * dr + di * di) / den)))
+    del A, B, A_cm, B_cm, C_cm
+    torch.cuda.empty_cache()
+    return dict(workload=f"square ZGEMM m=n=k={size}, real and imaginary parts "
+                         f"(rand-0.5)*exp({phi}*randn) seed {seed}, revised scaling, N={N}",
+                N=N, ms_per_step=round(ms, 4), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                flops_per_step="8mnk", stage_ms_per_step=st,
+                int8_gemm_top_s=round(k3_ops / (k3_ms * 1e-3) / 1e12, 1),
+                int8_gemm_frac=round(k3_ops / (k3_ms * 1e-3) / 1e12 / INT8_PEAK_TOPS, 4),
+                native_zgemm_tflops=round(native, 2), sampled_entries=samples,
+                max_rel_err_sampled=worst)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +316,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip the leg with N picked by the autotuner for --target")
+    ap.add_argument("--no-complex", action="store_true", help="skip the ZGEMM leg")
+    ap.add_argument("--complex-size", type=int, default=8192)
     ap.add_argument("--target", type=float, default=1e-15,
                     help="max relative error target of the fixed-error and batched legs")
     ap.add_argument("--traffic-calibration", type=int, default=0, metavar="BYTES",
@@ -361,6 +448,13 @@ def main():
              f"{batched['tflops_plain']} TFLOPS plain ({batched['speedup']}x), "
              f"N {batched['N_histogram']}, max rel err {batched['max_rel_err_sampled']:.2e}")
 
+    cplx = None
+    if not args.no_complex:
+        cplx = complex_leg(args.complex_size, N, args.phi, args.seed, args.steps, args.warmup)
+        _log(f"zgemm {args.complex_size}^3 N={N}: {cplx['tflops']} TFLOPS (8mnk/t) vs native "
+             f"{cplx['native_zgemm_tflops']}; INT8 GEMMs at {cplx['int8_gemm_top_s']} TOP/s; "
+             f"max rel err {cplx['max_rel_err_sampled']:.2e}")
+
     out = {
         "metric": "Emulated DGEMM TFLOPS (2mnk/t) at fixed max rel. error; batched vs plain",
         "value": round(value, 2),
@@ -390,6 +484,7 @@ def main():
         "sample_check": sample_check,
         "fixed_error": fixed,
         "batched": batched,
+        "complex": cplx,
         "context": {"paper_gh200_cublas_dgemm_tflops": 60.9,
                     "paper_gh200_ozaki2_dgemm_tflops_up_to": 80.2},
     }

@@ -110,6 +110,56 @@ int ozaki2_sgemm(int64_t m, int64_t n, int64_t k,
                  float* C, int64_t ldc,
                  int N, int mode);
 
+/*
+ * ozaki2_zgemm -- C ~ A B for complex binary64 matrices (ZGEMM).  The paper
+ * states that its scaling serves the complex fast mode as well (Section 1)
+ * and leaves the extension to future work (Section 6); the library applies
+ * Section 2.2 and Algorithm 2 (or 1) as follows.  A complex row of A (column
+ * of B) is scaled as the real vector of its 2k components in storage order
+ * (re, im, re, ...): squared norms rounded up over those components in
+ * chunks of 64 (32 complex entries), Algorithm 1's maximum over component
+ * magnitudes.  Both parts of an entry are truncated with the row's
+ * (column's) exponent; the CRT recovers the real and imaginary parts of the
+ * complex integer product exactly (both are bounded by ||a'_i|| ||b'_j||,
+ * what the scaling keeps below P/2), and each part of C is rounded once.
+ * Per modulus the product takes three INT8 GEMMs.
+ *
+ *   A, B, C   device pointers to interleaved (re, im) binary64 pairs
+ *             (the layout of hipDoubleComplex / double _Complex), column-major,
+ *             each aligned to 16 bytes (else -4, -6 or -8).
+ *   lda, ldb, ldc, m, n, k, N: as ozaki2_dgemm, leading dimensions counted
+ *             in complex entries.
+ *   mode      OZ2_MODE_REVISED or OZ2_MODE_ORIGINAL; OZ2_MODE_ACCURATE
+ *             returns OZ2_ERR_UNSUPPORTED.
+ *
+ * k up to OZ2_K_MAX (k-blocked beyond OZ2_K_BLOCK like ozaki2_dgemm).  A row
+ * or column with a non-finite entry or squared norm gives NaN in both parts
+ * of its outputs and sets OZ2_STATUS_NONFINITE.  Workspace and stream rules
+ * as ozaki2_dgemm (size: ozaki2_zgemm_workspace_size).
+ */
+int ozaki2_zgemm(int64_t m, int64_t n, int64_t k,
+                 const double* A, int64_t lda,
+                 const double* B, int64_t ldb,
+                 double* C, int64_t ldc,
+                 int N, int mode);
+
+/*
+ * ozaki2_cgemm -- as ozaki2_zgemm for complex binary32 matrices (CGEMM):
+ * pointers to interleaved binary32 pairs aligned to 8 bytes; squared norms in
+ * binary64 with rounding up; each part of C rounded once to binary32.
+ */
+int ozaki2_cgemm(int64_t m, int64_t n, int64_t k,
+                 const float* A, int64_t lda,
+                 const float* B, int64_t ldb,
+                 float* C, int64_t ldc,
+                 int N, int mode);
+
+/* Bytes of workspace an ozaki2_zgemm or ozaki2_cgemm call with these
+ * arguments needs (written to *bytes).  Returns 0, the argument error code,
+ * or OZ2_ERR_UNSUPPORTED for accurate mode. */
+int ozaki2_zgemm_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode,
+                                size_t* bytes);
+
 /* Set the HIP stream (a hipStream_t passed as void*; NULL = null stream)
  * used by every later call.  Returns 0. */
 int ozaki2_set_stream(void* stream);

@@ -17,6 +17,7 @@
 #include "oz2_k4_crt.hpp"
 #include "oz2_tables.hpp"
 #include "oz2_batched.hpp"
+#include "oz2_complex.hpp"
 
 #include <algorithm>
 
@@ -104,13 +105,16 @@ int tile_config(int64_t m, int64_t n, int64_t k, int N) {
   return g_tile_policy == OZ2_TILE_AUTO ? choose_tile(m, n, k, N) : g_tile_policy;
 }
 
+// comps = 1 for real products; 3 for complex ones (three residue planes per
+// modulus and operand, three uint8 product planes per modulus; the squared
+// norms run over 2k components).
 Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm = kBM,
-                   int64_t bn = kBN) {
+                   int64_t bn = kBN, int comps = 1) {
   Layout L;
   L.Mp = round_up(m > 0 ? m : 1, bm);
   L.Np = round_up(n > 0 ? n : 1, bn);
   L.Kp = round_up(k > 0 ? k : 1, kBK);
-  L.nch = (k + kKC - 1) / kKC;
+  L.nch = ((comps == 3 ? 2 * k : k) + kKC - 1) / kKC;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.status = take(256);
@@ -130,9 +134,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm 
   L.cmaxB = acc ? take(4 * (size_t)L.Np) : 0;
   L.barA = acc ? take((size_t)L.Mp * L.Kp) : 0;
   L.barB = acc ? take((size_t)L.Np * L.Kp) : 0;
-  L.RA = take((size_t)N * L.Mp * L.Kp);
-  L.RB = take((size_t)N * L.Np * L.Kp);
-  L.U = take((size_t)N * L.Mp * L.Np);
+  L.RA = take((size_t)comps * N * L.Mp * L.Kp);
+  L.RB = take((size_t)comps * N * L.Np * L.Kp);
+  L.U = take((size_t)comps * N * L.Mp * L.Np);
   L.total = off;
   return L;
 }
@@ -429,6 +433,107 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   return 0;
 }
 
+// Complex products (ZGEMM: T = double, CGEMM: T = float).  A, B and C hold
+// interleaved (re, im) pairs, column-major, leading dimensions in complex
+// entries.  Revised and original fast modes.
+template <typename T>
+int run_complex(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
+                int64_t ldb, T* C, int64_t ldc, int N, int mode) {
+  int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, N, mode, true);
+  if (rc) return rc;
+  if (mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
+  const uintptr_t align = 2 * sizeof(T) - 1;   // one complex entry
+  if (reinterpret_cast<uintptr_t>(A) & align) return -4;
+  if (reinterpret_cast<uintptr_t>(B) & align) return -6;
+  if (reinterpret_cast<uintptr_t>(C) & align) return -8;
+  if (m == 0 || n == 0) return 0;
+  int dev;
+  if ((rc = ensure_device(&dev))) return rc;
+  DevState& D = g_dev[dev];
+  if (k == 0) {
+    k_zero<T><<<(unsigned)((2 * m * n + 255) / 256), 256, 0, g_stream>>>(C, 2 * m, n, 2 * ldc);
+    return hipGetLastError() == hipSuccess ? 0 : OZ2_ERR_HIP;
+  }
+  build_host_tables();
+  if (!g_host_tables_ok[0][N]) return OZ2_ERR_UNSUPPORTED;
+  const ModTable& HT = g_host_tables[0][N];
+  const ModTable* tab = D.d_tables + N;
+
+  const int cfg = tile_config(m, n, k, N);
+  Layout L = make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg], 3);
+  char* ws = nullptr;
+  if ((rc = get_workspace(dev, L.total, &ws))) return rc;
+
+  StageClock clk;
+  clk.mark(0);
+  // K1: squared norms over the 2k components and exponents.
+  k_clear_status<<<1, 64, 0, g_stream>>>((int*)(ws + L.status));
+  {
+    double* pmA = L.maxA ? (double*)(ws + L.maxA) : nullptr;
+    double* pmB = L.maxB ? (double*)(ws + L.maxB) : nullptr;
+    dim3 gA((unsigned)((m + 63) / 64), (unsigned)((L.nch + 3) / 4));
+    k1_partials_strided_cplx<T><<<gA, 256, 0, g_stream>>>(A, lda, m, k, L.nch,
+                                                          (double*)(ws + L.partA), pmA);
+    int64_t work = n * L.nch;
+    k1_partials_contig<T><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
+        B, 2 * ldb, n, 2 * k, L.nch, (double*)(ws + L.partB), pmB);
+    k1_fold<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+        (double*)(ws + L.partA), pmA, L.nch, m, mode, tab, (int32_t*)(ws + L.eA),
+        (double*)(ws + L.SA), (int*)(ws + L.status));
+    k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+        (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
+        (double*)(ws + L.SB), (int*)(ws + L.status));
+  }
+  clk.mark(1);
+  // K2: integers and the residues of the three components.
+  {
+    const int64_t gx = L.Mp / kK2CVB;
+    const int64_t blocksA = gx * (L.Kp / kK2CHB);
+    const int64_t workB = L.Np * (L.Kp / kK2CEPL);
+    const int32_t* eA = (const int32_t*)(ws + L.eA);
+    const int32_t* eB = (const int32_t*)(ws + L.eB);
+    int8_t* RA = (int8_t*)(ws + L.RA);
+    int8_t* RB = (int8_t*)(ws + L.RB);
+    if (HT.limbs == 2) {
+      k2_split_strided_cplx<T, 2><<<(unsigned)blocksA, 256, 0, g_stream>>>(
+          A, lda, m, k, eA, tab, N, RA, L.Mp, L.Kp, gx);
+      k2_split_contig_cplx<T, 2><<<(unsigned)((workB + 255) / 256), 256, 0, g_stream>>>(
+          B, ldb, n, k, eB, tab, N, RB, L.Np, L.Kp);
+    } else {
+      k2_split_strided_cplx<T, 3><<<(unsigned)blocksA, 256, 0, g_stream>>>(
+          A, lda, m, k, eA, tab, N, RA, L.Mp, L.Kp, gx);
+      k2_split_contig_cplx<T, 3><<<(unsigned)((workB + 255) / 256), 256, 0, g_stream>>>(
+          B, ldb, n, k, eB, tab, N, RB, L.Np, L.Kp);
+    }
+  }
+  clk.mark(2);
+  // K3: 3N INT8 GEMMs, one launch (per k block) for each component.
+  for (int c = 0; c < 3; ++c)
+    launch_gemm_blocked(cfg, (const int8_t*)(ws + L.RA) + (size_t)c * N * L.Mp * L.Kp,
+                        (const int8_t*)(ws + L.RB) + (size_t)c * N * L.Np * L.Kp,
+                        (uint8_t*)(ws + L.U) + (size_t)c * N * L.Mp * L.Np, m, n, L, tab, N);
+  clk.mark(3);
+  // K4: both parts, CRT and unscaling.
+  {
+    const int64_t blocks = ((m + 31) / 32) * ((n + 31) / 32);
+    const unsigned grid = (unsigned)((blocks + 3) / 4);
+    const uint8_t* U = (const uint8_t*)(ws + L.U);
+    const int32_t* eA = (const int32_t*)(ws + L.eA);
+    const int32_t* eB = (const int32_t*)(ws + L.eB);
+    switch (HT.slices) {
+      case 1: k4_crt_cplx<1, T><<<grid, 256, 0, g_stream>>>(U, eA, eB, tab, N, m, n, L.Mp, L.Np, C, ldc); break;
+      case 2: k4_crt_cplx<2, T><<<grid, 256, 0, g_stream>>>(U, eA, eB, tab, N, m, n, L.Mp, L.Np, C, ldc); break;
+      case 3: k4_crt_cplx<3, T><<<grid, 256, 0, g_stream>>>(U, eA, eB, tab, N, m, n, L.Mp, L.Np, C, ldc); break;
+      default: k4_crt_cplx<4, T><<<grid, 256, 0, g_stream>>>(U, eA, eB, tab, N, m, n, L.Mp, L.Np, C, ldc); break;
+    }
+  }
+  clk.mark(4);
+  clk.mark(5);
+  if (hipGetLastError() != hipSuccess) return OZ2_ERR_HIP;
+  clk.finish();
+  return 0;
+}
+
 // ---------------------------------------------------------------------------
 // Batched path: graph built once per batch signature, replayed per call.
 // ---------------------------------------------------------------------------
@@ -705,6 +810,27 @@ int ozaki2_dgemm(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
 int ozaki2_sgemm(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
                  const float* B, int64_t ldb, float* C, int64_t ldc, int N, int mode) {
   return run_gemm<float, float>(m, n, k, A, lda, B, ldb, C, ldc, N, mode, nullptr);
+}
+
+int ozaki2_zgemm(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                 const double* B, int64_t ldb, double* C, int64_t ldc, int N, int mode) {
+  return run_complex<double>(m, n, k, A, lda, B, ldb, C, ldc, N, mode);
+}
+
+int ozaki2_cgemm(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
+                 const float* B, int64_t ldb, float* C, int64_t ldc, int N, int mode) {
+  return run_complex<float>(m, n, k, A, lda, B, ldb, C, ldc, N, mode);
+}
+
+int ozaki2_zgemm_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode,
+                                size_t* bytes) {
+  int rc = check_args(m, n, k, (const void*)16, m > 1 ? m : 1, (const void*)16, k > 1 ? k : 1,
+                      (const void*)16, m > 1 ? m : 1, N, mode, true);
+  if (rc) return rc;
+  if (mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
+  if (!bytes) return -6;
+  *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(m, n, k, N, mode, kBM, kBN, 3).total;
+  return 0;
 }
 
 int ozaki2_set_stream(void* stream) {

@@ -5,9 +5,10 @@ pointer arguments accept a torch tensor (its ``data_ptr()``) or an int.  All
 computation happens in the HIP library; if it is not built or cannot be
 loaded, the first call raises.
 
-``dgemm``/``sgemm`` are conveniences for row-major torch tensors on the GPU:
-a row-major m x k tensor is the column-major k x m matrix, so C = A B is
-computed as the column-major C^T = B^T A^T by swapping the operands.
+``dgemm``/``sgemm``/``zgemm``/``cgemm`` are conveniences for row-major torch
+tensors on the GPU: a row-major m x k tensor is the column-major k x m
+matrix, so C = A B is computed as the column-major C^T = B^T A^T by swapping
+the operands (a plain transpose, also for complex tensors).
 """
 from __future__ import annotations
 
@@ -36,6 +37,10 @@ class Oz2Problem(ctypes.Structure):
 _SIGS = {
     "ozaki2_dgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
     "ozaki2_sgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_zgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_cgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_zgemm_workspace_size": ([_c_i64] * 3 + [_c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)],
+                                    _c_int),
     "ozaki2_set_stream": ([_vp], _c_int),
     "ozaki2_workspace_size": ([_c_i64] * 3 + [_c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)], _c_int),
     "ozaki2_set_workspace": ([_vp, ctypes.c_size_t], _c_int),
@@ -103,6 +108,21 @@ def ozaki2_dgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
 
 def ozaki2_sgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
     return lib().ozaki2_sgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_zgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
+    return lib().ozaki2_zgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_cgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
+    return lib().ozaki2_cgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_zgemm_workspace_size(m, n, k, N, mode=MODE_REVISED):
+    b = ctypes.c_size_t(0)
+    _check("ozaki2_zgemm_workspace_size",
+           lib().ozaki2_zgemm_workspace_size(m, n, k, N, mode, ctypes.byref(b)))
+    return b.value
 
 
 def ozaki2_set_stream(stream):
@@ -226,6 +246,22 @@ def sgemm(A, B, N=7, mode="revised", out=None):
     if A.dtype != torch.float32 or B.dtype != torch.float32:
         raise TypeError("sgemm needs float32 tensors")
     return _gemm(A, B, N, mode, out, ozaki2_sgemm)
+
+
+def zgemm(A, B, N=14, mode="revised", out=None):
+    """C = A @ B for row-major complex128 CUDA tensors A (m x k), B (k x n)."""
+    import torch
+    if A.dtype != torch.complex128 or B.dtype != torch.complex128:
+        raise TypeError("zgemm needs complex128 tensors")
+    return _gemm(A, B, N, mode, out, ozaki2_zgemm)
+
+
+def cgemm(A, B, N=7, mode="revised", out=None):
+    """C = A @ B for row-major complex64 CUDA tensors A (m x k), B (k x n)."""
+    import torch
+    if A.dtype != torch.complex64 or B.dtype != torch.complex64:
+        raise TypeError("cgemm needs complex64 tensors")
+    return _gemm(A, B, N, mode, out, ozaki2_cgemm)
 
 
 def _gemm(A, B, N, mode, out, fn):

@@ -5,6 +5,7 @@
     python -m paper_2606_29129_amd.sweep scale
     python -m paper_2606_29129_amd.sweep accuracy [--block 512]
     python -m paper_2606_29129_amd.sweep sgemm [--sizes 4096,8192,16384]
+    python -m paper_2606_29129_amd.sweep complex [--sizes 4096,8192] [--zNs ...] [--cNs ...]
 
 Every result is one JSON line on stdout.
 
@@ -28,6 +29,9 @@ Every result is one JSON line on stdout.
 
 * ``sgemm``: binary32 emulation (Section 5) over sizes for N = 5..9 beside
   native binary32 ``torch.matmul``.
+* ``complex``: ZGEMM and CGEMM emulation (8mnk/t) over sizes and N beside
+  native complex ``torch.matmul``; errors per part against a double-double
+  reference (Re = [Re A, -Im A][Re B; Im B], Im = [Re A, Im A][Im B; Re B]).
 
 Errors: ``max_rel`` = max |C - R| / |R| over R != 0 (``zero_ref_nonzero``
 counts R = 0 with C != 0), ``max_cw`` = max |C - R| / (|A||B|)_ij.  The
@@ -387,9 +391,87 @@ def sweep_accuracy(args):
         P.release()
 
 
+def _complex_block(Ah, Bh):
+    """Double-double reference of both parts of a complex block product, with
+    the componentwise scales (|Re A||Re B| + |Im A||Im B| for the real part,
+    |Re A||Im B| + |Im A||Re B| for the imaginary part)."""
+    xr, xi, ur, ui = Ah.real, Ah.imag, Bh.real, Bh.imag
+    re = dd_block(np.hstack([xr, -xi]), np.vstack([ur, ui]))
+    im = dd_block(np.hstack([xr, xi]), np.vstack([ui, ur]))
+    are = np.abs(xr) @ np.abs(ur) + np.abs(xi) @ np.abs(ui)
+    aim = np.abs(xr) @ np.abs(ui) + np.abs(xi) @ np.abs(ur)
+    return (re, are), (im, aim)
+
+
+def _complex_errors(C, blocks):
+    (re, are), (im, aim) = blocks
+    er, ei = errors(C.real, re, are), errors(C.imag, im, aim)
+    return dict(max_rel=max(er["max_rel"], ei["max_rel"]),
+                max_cw=max(er["max_cw"], ei["max_cw"]),
+                zero_ref_nonzero=er["zero_ref_nonzero"] + ei["zero_ref_nonzero"])
+
+
+def sweep_complex(args):
+    """ZGEMM (complex128) and CGEMM (complex64) emulation: 8mnk/t over sizes
+    and N beside native complex torch.matmul of the same GPU, per-stage
+    times, the INT8 rate of the 3N GEMMs, and errors per part on a sampled
+    block against a double-double reference."""
+    import torch
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.sizes.split(",")]
+    phi = float(args.phis.split(",")[0])
+    rng = np.random.default_rng(0)
+    for S in sizes:
+        A = inputs.complex_matrix_torch(S, S, phi, 0, 0, dev)
+        B = inputs.complex_matrix_torch(S, S, phi, 0, 1, dev)
+        rows = np.sort(rng.choice(S, args.sample, replace=False))
+        cols = np.sort(rng.choice(S, args.sample, replace=False))
+        rt, ctt = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+        for single in (False, True):
+            dt = torch.complex64 if single else torch.complex128
+            Au, Bu = A.to(dt), B.to(dt)
+            Ah = Au[rt].to(torch.complex128).cpu().numpy()
+            Bh = Bu[:, ctt].to(torch.complex128).cpu().numpy()
+            blocks = _complex_block(Ah, Bh)
+            nat_ms, Cn = _native_ms(torch, Au, Bu)
+            nat_err = _complex_errors(Cn[rt][:, ctt].to(torch.complex128).cpu().numpy(), blocks)
+            del Cn
+            flops = 8.0 * S ** 3
+            name = "cgemm" if single else "zgemm"
+            _emit(dict(leg="complex", op=name, m=S, n=S, k=S, phi=phi,
+                       method="native torch.matmul", tflops=round(flops / nat_ms / 1e9, 2),
+                       sample=f"{args.sample}x{args.sample} block", **nat_err))
+            A_cm, B_cm = Au.t().contiguous(), Bu.t().contiguous()
+            C_cm = torch.empty((S, S), dtype=dt, device=dev)
+            oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+            fn = oz.ozaki2_cgemm if single else oz.ozaki2_zgemm
+            Ns = [int(x) for x in (args.cNs if single else args.zNs).split(",")]
+            for N in Ns:
+                def run():
+                    rc = fn(S, S, S, A_cm, S, B_cm, S, C_cm, S, N, 0)
+                    if rc:
+                        raise oz.Ozaki2Error(fn.__name__, rc)
+                ms, st = _timed(torch, run, args.steps, args.warmup)
+                k3 = st["int8_gemm"]
+                C = C_cm.index_select(0, ctt).index_select(1, rt).t()
+                _emit(dict(leg="complex", op=name, m=S, n=S, k=S, phi=phi,
+                           method="ozaki2 revised", N=N, ms=round(ms, 4),
+                           tflops=round(flops / ms / 1e9, 2), stage_ms=st,
+                           int8_mfma_util=round(6.0 * N * S ** 3 / (k3 * 1e-3) / 1e12
+                                                / INT8_PEAK_TOPS, 4) if k3 > 0 else None,
+                           native_tflops=round(flops / nat_ms / 1e9, 2),
+                           sample=f"{args.sample}x{args.sample} block",
+                           **_complex_errors(C.to(torch.complex128).cpu().numpy(), blocks)))
+            del A_cm, B_cm, C_cm, Au, Bu
+            torch.cuda.empty_cache()
+        del A, B
+        torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy", "sgemm"])
+    ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy", "sgemm",
+                                    "complex"])
     ap.add_argument("--sizes", default="1024,4096,8192,16384")
     ap.add_argument("--phis", default="0.5,1,2,4")
     ap.add_argument("--Ns", default="12,14,16,18,20")
@@ -399,9 +481,11 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=512, help="sampled block edge (accuracy leg)")
     ap.add_argument("--acc-size", type=int, default=8192)
     ap.add_argument("--scale-size", type=int, default=4096)
+    ap.add_argument("--zNs", default="12,14,16,18", help="N list of the ZGEMM runs")
+    ap.add_argument("--cNs", default="5,6,7,8", help="N list of the CGEMM runs")
     a = ap.parse_args(argv)
     {"throughput": sweep_throughput, "shapes": sweep_shapes, "scale": sweep_scale,
-     "accuracy": sweep_accuracy, "sgemm": sweep_sgemm}[a.leg](a)
+     "accuracy": sweep_accuracy, "sgemm": sweep_sgemm, "complex": sweep_complex}[a.leg](a)
 
 
 if __name__ == "__main__":

@@ -118,3 +118,36 @@ def test_k_limits_of_the_header():
     prob = oz.Oz2Problem(4, 4, 2**17 + 1, 8, 4, 8, 2**17 + 1, 8, 4, 14, 0)
     arr = (oz.Oz2Problem * 1)(prob)
     assert oz.lib().ozaki2_dgemm_batched(1, arr, 0, ctypes.byref(bad)) == 1 and bad.value == 0
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 1, 16, 1, 16, 1, 16, 1, 14, 0), -1),
+    ((4, 4, 4, 16, 3, 16, 4, 16, 4, 14, 0), -5),
+    ((4, 4, 4, 16, 4, 16, 4, 16, 4, 21, 0), -10),
+    ((4, 4, 4, 16, 4, 16, 4, 16, 4, 14, 3), -11),
+    ((4, 4, 4, 16, 4, 16, 4, 16, 4, 14, 2), 4),     # accurate mode: unsupported
+    ((4, 4, 4, 24, 4, 16, 4, 16, 4, 14, 0), -4),    # A not aligned to a complex entry
+    ((4, 4, 4, 16, 4, 40, 4, 16, 4, 14, 0), -6),
+    ((4, 4, 4, 16, 4, 16, 4, 56, 4, 14, 0), -8),
+    ((4, 4, 2**22 + 1, 16, 4, 16, 2**22 + 1, 16, 4, 14, 0), 1),
+])
+def test_complex_argument_errors_without_device_work(args, code):
+    assert oz.ozaki2_zgemm(*args) == code
+    if code in (-4, -6, -8):
+        # binary32 pairs need 8-byte alignment only: 24, 40 and 56 are fine
+        return
+    assert oz.ozaki2_cgemm(*args) == code
+
+
+def test_cgemm_alignment_is_one_complex64_entry():
+    assert oz.ozaki2_cgemm(4, 4, 4, 20, 4, 16, 4, 16, 4, 14, 0) == -4
+    assert oz.ozaki2_cgemm(0, 4, 4, 16, 1, 16, 4, 16, 1, 14, 0) == 0   # quick return
+
+
+def test_complex_workspace_holds_three_components():
+    r = oz.ozaki2_workspace_size(1024, 1024, 1024, 14)
+    z = oz.ozaki2_zgemm_workspace_size(1024, 1024, 1024, 14)
+    assert 3 * (r - 2**20) < z < 3 * r + 2**20
+    assert oz.ozaki2_zgemm_workspace_size(0, 5, 5, 14) == 0
+    with pytest.raises(oz.Ozaki2Error):
+        oz.ozaki2_zgemm_workspace_size(8, 8, 8, 14, 2)
