@@ -26,14 +26,17 @@ Algorithm 1) to complex matrices under the following readings:
 * Step 4 rounds each part once, to nearest even, in the output format.
 
 Accurate mode is not defined here (its bound product would need complex
-magnitudes, which the paper does not discuss).
+magnitudes, which the paper does not discuss).  The exact mode (an optional
+variant, ``scaling.exact_mode_log2_mu``) applies to the 2k components as
+well.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import constants, fp, scaling
-from .ozaki2 import ORIGINAL, REVISED, residue, residues, rmod, scaled_integer, step2, step4
+from .ozaki2 import (EXACT, ORIGINAL, REVISED, residue, residues, rmod, scaled_integer, step2,
+                     step4)
 
 
 def components(v) -> np.ndarray:
@@ -53,6 +56,11 @@ def scale_exponents(A, B, N: int, mode: int = REVISED):
     B = np.asarray(B, dtype=np.complex128)
     rows = [components(A[i, :]) for i in range(A.shape[0])]
     cols = [components(B[:, j]) for j in range(B.shape[1])]
+    if mode == EXACT:
+        _, P, _, _ = constants.step1(N)
+        ra = [scaling.exact_mode_log2_mu(r, P) for r in rows]
+        rb = [scaling.exact_mode_log2_mu(c, P) for c in cols]
+        return [e for e, _ in ra], [e for e, _ in rb], [S for _, S in ra], [S for _, S in rb]
     SA = [scaling.norm_sq_ru(r) for r in rows]
     SB = [scaling.norm_sq_ru(c) for c in cols]
     if mode == REVISED:

@@ -29,7 +29,7 @@ import numpy as np
 
 from . import constants, fp, scaling
 
-REVISED, ORIGINAL, ACCURATE = 0, 1, 2
+REVISED, ORIGINAL, ACCURATE, EXACT = 0, 1, 2, 3
 
 
 def round_half_even_div(x: int, P: int) -> int:
@@ -126,12 +126,23 @@ def scale_exponents(A, B, N: int, mode: int = REVISED):
         emu, enu, _, _, _ = scaling.accurate_log2(
             A, B, constants.p_prime_accu(N), constants.delta())
         return emu, enu, None, None
-    SA = [scaling.norm_sq_ru(A[i, :]) for i in range(A.shape[0])]
-    SB = [scaling.norm_sq_ru(B[:, j]) for j in range(B.shape[1])]
+    if mode == EXACT:
+        SA = SB = None
+    else:
+        SA = [scaling.norm_sq_ru(A[i, :]) for i in range(A.shape[0])]
+        SB = [scaling.norm_sq_ru(B[:, j]) for j in range(B.shape[1])]
     if mode == REVISED:
         pp = constants.p_prime_prop(N)
         emu = [scaling.alg2_log2_mu(S, pp) for S in SA]
         enu = [scaling.alg2_log2_mu(S, pp) for S in SB]
+    elif mode == EXACT:
+        # squared norms recomputed per vector (the overflow fallback may
+        # replace them): the norms returned are the ones the exponents used
+        _, P, _, _ = constants.step1(N)
+        ra = [scaling.exact_mode_log2_mu(A[i, :], P) for i in range(A.shape[0])]
+        rb = [scaling.exact_mode_log2_mu(B[:, j], P) for j in range(B.shape[1])]
+        emu, SA = [e for e, _ in ra], [S for _, S in ra]
+        enu, SB = [e for e, _ in rb], [S for _, S in rb]
     elif mode == ORIGINAL:
         pf, d = constants.p_prime_fast(N), constants.delta()
         amaxA = [float(np.max(np.abs(A[i, :]))) for i in range(A.shape[0])]

@@ -5,6 +5,10 @@
 * ``alg2_log2_mu``     Algorithm 2, the proposed scaling (Section 4)
 * ``alg1_log2_mu``     Algorithm 1, the original fast mode (Section 2.3)
 * ``accurate_log2``    accurate mode (Section 2.3)
+* ``emax_log2_mu``, ``exact_mode_log2_mu``  the exact mode, an optional
+                       variant (not in the paper): the exact maximal exponent
+                       of the Cauchy-Schwarz condition, with an overflow
+                       fallback for huge rows
 
 Every rounding is done exactly on rationals (``oracle.fp``).
 
@@ -104,6 +108,66 @@ def alg1_log2_mu(S: float, amax: float, p_fast: Fraction, delta: Fraction) -> in
     L = fp.log2_rn32(fp.ru32(x))
     t = fp.ru32(Fraction(delta) * fp.ru32(L + s))
     return math.floor(Fraction(p_fast) - max(Fraction(1), t)) - fp.floor_log2(Fraction(amax))
+
+
+# --- exact mode (not in the paper: an optional variant of Algorithm 2) -------
+
+RESCALE = 600   # exponent shift of the overflow fallback of the exact mode
+
+
+def emax_log2_mu(S: float, P: int) -> int:
+    """Exact maximal exponent: the largest integer e with
+    2**(2e+1) * S <= P - 1, by exact rational comparison (S >= 0 finite).
+
+    This is the condition Section 4 derives from Cauchy-Schwarz (the product
+    of the two scaled norms at most (P-1)/2) with S an upper bound of the
+    squared norm; Algorithm 2 reaches it up to its binary32 slack (it returns
+    this value or one less on ordinary data).  A zero vector gets 0.
+    """
+    if not math.isfinite(S):
+        raise OverflowError("non-finite squared norm")
+    if S == 0.0:
+        return 0
+    x = Fraction(S)
+    # 2**(2e+1) x <= P - 1 < 2**(LP+1) with x >= 2**Lx gives e <= (LP - Lx) / 2
+    e = (fp.floor_log2(Fraction(P - 1)) - fp.floor_log2(x)) // 2
+    while fp._pow2(2 * e + 1) * x > P - 1:
+        e -= 1
+    return e
+
+
+def norm_sq_ru_rescaled(v, shift: int = -RESCALE) -> float:
+    """``norm_sq_ru`` of the entries scaled by 2**shift, each scaled
+    magnitude rounded up to binary64 (so tiny entries that underflow still
+    count, and the result times 4**-shift bounds the squared norm)."""
+    scaled = []
+    for a in np.asarray(v, dtype=np.float64).ravel():
+        a = abs(float(a))
+        if not math.isfinite(a):
+            scaled.append(a)
+        else:
+            scaled.append(float(fp.round_rational(Fraction(a) * fp._pow2(shift),
+                                                  fp.BINARY64, "RU")))
+    return norm_sq_ru(scaled)
+
+
+def exact_mode_log2_mu(v, P: int):
+    """Exact mode: (log2 mu, the squared norm used).
+
+    The squared norm is ``norm_sq_ru(v)``; where it overflows binary64 (an
+    entry or the sum beyond about 1.3e154) the entries are scaled by 2**-600
+    first (``norm_sq_ru_rescaled``) and the exponent is shifted back by 600.
+    NaN, or an infinite entry, stays non-finite (OverflowError).
+    """
+    S = norm_sq_ru(v)
+    if math.isnan(S):
+        raise OverflowError("NaN in the vector")
+    if math.isinf(S):
+        S2 = norm_sq_ru_rescaled(v)
+        if not math.isfinite(S2):
+            raise OverflowError("infinite entry")
+        return emax_log2_mu(S2, P) - RESCALE, S2
+    return emax_log2_mu(S, P), S
 
 
 def tilde_log2_ru(x: int) -> Fraction:
