@@ -43,6 +43,17 @@ extern "C" {
 #define OZ2_MODE_REVISED  0 /* Section 4, Algorithm 2: the proposed scaling */
 #define OZ2_MODE_ORIGINAL 1 /* Section 2.3, Algorithm 1: original fast mode */
 #define OZ2_MODE_ACCURATE 2 /* Section 2.3: accurate mode (extra INT8 GEMM) */
+/* Exact mode: an optional variant of Algorithm 2 that is not in the paper.
+ * The exponent is the exact maximum of the condition Section 4 derives from
+ * Cauchy-Schwarz, e = max{e : 2^(2e+1) S <= P - 1} with S the rounded-up
+ * squared norm (Algorithm 2 returns this value, or one less within its
+ * binary32 slack); it is exactly scale invariant under powers of two.  Where
+ * S overflows binary64 (entries or norms beyond about 1.3e154) the norm is
+ * recomputed over the entries scaled by 2^-600 (magnitudes rounded up) and
+ * the exponent shifted back by 600, so such rows and columns are computed
+ * instead of returned as NaN.  Same cost as OZ2_MODE_REVISED when nothing
+ * overflows (two extra launches that exit at once). */
+#define OZ2_MODE_EXACT    3
 
 /* Status codes (positive; argument errors are negative). */
 #define OZ2_SUCCESS          0
@@ -55,9 +66,10 @@ extern "C" {
 #define OZ2_ERR_TOO_LARGE    5 /* a size overflows the library's indexing */
 
 /* Device status bits reported by ozaki2_get_device_status. */
-#define OZ2_STATUS_NONFINITE 1 /* a row/column had a NaN/Inf entry or a squared
-                                  norm that overflowed binary64; its output
-                                  row/column was written as NaN */
+#define OZ2_STATUS_NONFINITE 1 /* a row/column had a NaN/Inf entry or (other
+                                  than in OZ2_MODE_EXACT) a squared norm that
+                                  overflowed binary64; its output row/column
+                                  was written as NaN */
 
 /* Limits. */
 #define OZ2_N_MIN 2
@@ -129,8 +141,8 @@ int ozaki2_sgemm(int64_t m, int64_t n, int64_t k,
  *             each aligned to 16 bytes (else -4, -6 or -8).
  *   lda, ldb, ldc, m, n, k, N: as ozaki2_dgemm, leading dimensions counted
  *             in complex entries.
- *   mode      OZ2_MODE_REVISED or OZ2_MODE_ORIGINAL; OZ2_MODE_ACCURATE
- *             returns OZ2_ERR_UNSUPPORTED.
+ *   mode      OZ2_MODE_REVISED, OZ2_MODE_ORIGINAL or OZ2_MODE_EXACT;
+ *             OZ2_MODE_ACCURATE returns OZ2_ERR_UNSUPPORTED.
  *
  * k up to OZ2_K_MAX (k-blocked beyond OZ2_K_BLOCK like ozaki2_dgemm).  A row
  * or column with a non-finite entry or squared norm gives NaN in both parts

@@ -40,22 +40,26 @@ struct Cplx<float> { using type = float2; };
 // chunk as in the real strided kernel.  The columns of complex B need no
 // kernel of their own: their components are contiguous, so the real
 // contiguous kernel runs over 2k components with leading dimension 2 ldb.
-template <typename T>
+// RESC: the exact mode's fallback pass (vectors marked kExpRescale only,
+// entries scaled down), as in the real kernels.
+template <typename T, bool RESC = false>
 __global__ __launch_bounds__(256) void k1_partials_strided_cplx(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax) {
+    double* __restrict__ part, double* __restrict__ pmax,
+    const int32_t* __restrict__ esel = nullptr) {
   using T2 = typename Cplx<T>::type;
   constexpr int KH = kKC / 2;
   const int lane = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 64 + lane;
   const int64_t c = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
   if (v >= nvec || c >= nchunks) return;
+  if (RESC && esel[v] != kExpRescale) return;
   const int64_t h0 = c * KH;
   const int64_t len = k - h0 < KH ? k - h0 : KH;
   const T2* p = reinterpret_cast<const T2*>(X) + v + h0 * ld;
   double s = 0.0, mx = 0.0;
   auto add = [&](T2 z) {
-    const double a = (double)z.x, b = (double)z.y;
+    const double a = norm_entry<RESC>((double)z.x), b = norm_entry<RESC>((double)z.y);
     s = ru_add(s, ru_square(a));
     s = ru_add(s, ru_square(b));
     mx = fmax(mx, fmax(fabs(a), fabs(b)));

@@ -17,19 +17,42 @@ namespace oz2 {
 
 constexpr int kKC = 64;
 constexpr int32_t kExpNonFinite = INT32_MIN;  // exponent sentinel: NaN output
+constexpr int32_t kExpRescale = INT32_MIN + 2;  // exact mode: norm overflowed, recompute
+constexpr int kRescaleShift = 600;               // exact mode: entries scaled by 2^-600
+
+// Exact mode's overflow fallback: |a| 2^-600 rounded up in binary64 (the
+// scaling is exact unless the result is subnormal; scaling that result back
+// up is exact, so a shortfall shows and the magnitude is raised by one ulp).
+OZ2_HD double ru_scale_down(double a) {
+  const double x = fabs(a);
+  double r = ldexp(x, -kRescaleShift);
+  if (ldexp(r, kRescaleShift) < x) r = next_up_nonneg(r);
+  return r;
+}
+
+// Entry as summed by a partial-sum pass: itself, or (RESC) scaled down.
+template <bool RESC>
+OZ2_HD double norm_entry(double a) {
+  if constexpr (RESC) return ru_scale_down(a);
+  else return a;
+}
 
 // Vectors stored with stride `ld` between consecutive entries (rows of a
 // column-major matrix): entry h of vector v is X[v + h * ld].  One lane per
 // vector (64 consecutive vectors per wave, so every load is a contiguous 512
 // bytes), one wave per chunk.
-template <typename T>
+// RESC: the exact mode's second pass, only for vectors whose exponent is
+// kExpRescale (esel), summing the scaled-down entries.
+template <typename T, bool RESC = false>
 __device__ __forceinline__ void k1_partials_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax, int64_t bx, int64_t by) {
+    double* __restrict__ part, double* __restrict__ pmax, int64_t bx, int64_t by,
+    const int32_t* __restrict__ esel = nullptr) {
   const int lane = threadIdx.x & 63;
   const int64_t v = bx * 64 + lane;
   const int64_t c = by * 4 + (threadIdx.x >> 6);
   if (v >= nvec || c >= nchunks) return;
+  if (RESC && esel[v] != kExpRescale) return;
   const int64_t h0 = c * kKC;
   const int64_t len = k - h0 < kKC ? k - h0 : kKC;
   const T* p = X + v + h0 * ld;
@@ -39,7 +62,7 @@ __device__ __forceinline__ void k1_partials_strided_body(
     for (int b = 0; b < kKC; b += 16) {
       double a[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = (double)p[(int64_t)(b + i) * ld];
+      for (int i = 0; i < 16; ++i) a[i] = norm_entry<RESC>((double)p[(int64_t)(b + i) * ld]);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         s = ru_add(s, ru_square(a[i]));
@@ -48,7 +71,7 @@ __device__ __forceinline__ void k1_partials_strided_body(
     }
   } else {
     for (int64_t h = 0; h < len; ++h) {
-      double a = (double)p[h * ld];
+      double a = norm_entry<RESC>((double)p[h * ld]);
       s = ru_add(s, ru_square(a));
       mx = fmax(mx, fabs(a));
     }
@@ -57,24 +80,28 @@ __device__ __forceinline__ void k1_partials_strided_body(
   if (pmax) pmax[c * nvec + v] = mx;
 }
 
-template <typename T>
+template <typename T, bool RESC = false>
 __global__ __launch_bounds__(256) void k1_partials_strided(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax) {
-  k1_partials_strided_body<T>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x, blockIdx.y);
+    double* __restrict__ part, double* __restrict__ pmax,
+    const int32_t* __restrict__ esel = nullptr) {
+  k1_partials_strided_body<T, RESC>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x, blockIdx.y,
+                                    esel);
 }
 
 // Vectors stored contiguously (columns of a column-major matrix): entry h of
 // vector v is X[h + v * ld].  One lane per (vector, chunk); lanes of a wave
 // take consecutive chunks.
-template <typename T>
+template <typename T, bool RESC = false>
 __device__ __forceinline__ void k1_partials_contig_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax, int64_t bx) {
+    double* __restrict__ part, double* __restrict__ pmax, int64_t bx,
+    const int32_t* __restrict__ esel = nullptr) {
   const int64_t g = bx * 256 + threadIdx.x;
   if (g >= nvec * nchunks) return;
   const int64_t v = g / nchunks;
   const int64_t c = g - v * nchunks;
+  if (RESC && esel[v] != kExpRescale) return;
   const int64_t h0 = c * kKC;
   const int64_t len = k - h0 < kKC ? k - h0 : kKC;
   const T* p = X + v * ld + h0;
@@ -84,7 +111,7 @@ __device__ __forceinline__ void k1_partials_contig_body(
     for (int b = 0; b < kKC; b += 16) {
       double a[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = (double)p[b + i];
+      for (int i = 0; i < 16; ++i) a[i] = norm_entry<RESC>((double)p[b + i]);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         s = ru_add(s, ru_square(a[i]));
@@ -93,7 +120,7 @@ __device__ __forceinline__ void k1_partials_contig_body(
     }
   } else {
     for (int64_t h = 0; h < len; ++h) {
-      double a = (double)p[h];
+      double a = norm_entry<RESC>((double)p[h]);
       s = ru_add(s, ru_square(a));
       mx = fmax(mx, fabs(a));
     }
@@ -102,15 +129,18 @@ __device__ __forceinline__ void k1_partials_contig_body(
   if (pmax) pmax[c * nvec + v] = mx;
 }
 
-template <typename T>
+template <typename T, bool RESC = false>
 __global__ __launch_bounds__(256) void k1_partials_contig(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
-    double* __restrict__ part, double* __restrict__ pmax) {
-  k1_partials_contig_body<T>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x);
+    double* __restrict__ part, double* __restrict__ pmax,
+    const int32_t* __restrict__ esel = nullptr) {
+  k1_partials_contig_body<T, RESC>(X, ld, nvec, k, nchunks, part, pmax, blockIdx.x, esel);
 }
 
 // Pass 2: fold partial sums in chunk order and evaluate the exponent.
-// mode 0: Algorithm 2 (revised); mode 1: Algorithm 1 (original fast mode).
+// mode 0: Algorithm 2 (revised); mode 1: Algorithm 1 (original fast mode);
+// mode 3: the exact maximal exponent (an overflowing norm is marked for the
+// fallback pass instead of flagged).
 // A squared norm that is NaN or +inf yields the sentinel exponent and sets
 // bit OZ2_STATUS_NONFINITE in *status.
 // Fold the chunk sums of vector v left to right with rounded-up additions
@@ -153,13 +183,38 @@ __device__ __forceinline__ void k1_fold_body(
   fold_chunks(part, pmax, nchunks, nvec, v, &S, &mx);
   if (S_out) S_out[v] = S;
   int32_t e;
-  if (!(S <= 1.7976931348623157e308)) {
+  if (mode == 3 && S > 1.7976931348623157e308) {
+    e = kExpRescale;                  // +inf: the exact mode's fallback pass
+  } else if (!(S <= 1.7976931348623157e308)) {
     e = kExpNonFinite;
     atomicOr(status, 1);
   } else if (mode == 0) {
     e = alg2_exponent(S, tab->p_prop);
+  } else if (mode == 3) {
+    e = emax_exponent(S, tab->pm1_rd);
   } else {
     e = alg1_exponent(S, mx, tab->p_fast, tab->delta);
+  }
+  e_out[v] = e;
+}
+
+// Exact mode, fallback fold: for the vectors marked kExpRescale, fold the
+// partial sums of the scaled-down entries and shift the exponent back.
+__global__ __launch_bounds__(256) void k1_fold_rescale(
+    const double* __restrict__ part, int64_t nchunks, int64_t nvec,
+    const ModTable* __restrict__ tab, int32_t* __restrict__ e_out,
+    double* __restrict__ S_out, int* __restrict__ status) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= nvec || e_out[v] != kExpRescale) return;
+  double S, mx;
+  fold_chunks(part, nullptr, nchunks, nvec, v, &S, &mx);
+  if (S_out) S_out[v] = S;
+  int32_t e;
+  if (!(S <= 1.7976931348623157e308)) {   // an infinite entry
+    e = kExpNonFinite;
+    atomicOr(status, 1);
+  } else {
+    e = emax_exponent(S, tab->pm1_rd) - kRescaleShift;
   }
   e_out[v] = e;
 }

@@ -124,7 +124,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm 
   L.SB = take(8 * (size_t)n);
   L.partA = take(8 * (size_t)L.nch * m);
   L.partB = take(8 * (size_t)L.nch * n);
-  const bool need_max = (mode != OZ2_MODE_REVISED);
+  const bool need_max = (mode == OZ2_MODE_ORIGINAL || mode == OZ2_MODE_ACCURATE);
   L.maxA = need_max ? take(8 * (size_t)L.nch * m) : 0;
   L.maxB = need_max ? take(8 * (size_t)L.nch * n) : 0;
   const bool acc = (mode == OZ2_MODE_ACCURATE);
@@ -157,7 +157,8 @@ int check_args(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
     if (ldc < (m > 1 ? m : 1)) return -9;
   }
   if (N < OZ2_N_MIN || N > OZ2_N_MAX) return -10;
-  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL && mode != OZ2_MODE_ACCURATE)
+  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL && mode != OZ2_MODE_ACCURATE &&
+      mode != OZ2_MODE_EXACT)
     return -11;
   if (k > OZ2_K_MAX || (mode == OZ2_MODE_ACCURATE && k > OZ2_K_MAX_ACCURATE))
     return OZ2_ERR_K_TOO_LARGE;
@@ -350,6 +351,21 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
       k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
           (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
           (double*)(ws + L.SB), (int*)(ws + L.status));
+      if (mode == OZ2_MODE_EXACT) {
+        // Fallback for the vectors whose squared norm overflowed: the partial
+        // sums again over the scaled-down entries (other vectors exit at
+        // once), then their fold.
+        k1_partials_strided<T, true><<<gA, 256, 0, g_stream>>>(
+            A, lda, m, k, L.nch, (double*)(ws + L.partA), nullptr, (const int32_t*)(ws + L.eA));
+        k1_partials_contig<T, true><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
+            B, ldb, n, k, L.nch, (double*)(ws + L.partB), nullptr, (const int32_t*)(ws + L.eB));
+        k1_fold_rescale<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+            (double*)(ws + L.partA), L.nch, m, tab, (int32_t*)(ws + L.eA), (double*)(ws + L.SA),
+            (int*)(ws + L.status));
+        k1_fold_rescale<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+            (double*)(ws + L.partB), L.nch, n, tab, (int32_t*)(ws + L.eB), (double*)(ws + L.SB),
+            (int*)(ws + L.status));
+      }
     } else {
       // Accurate mode (Section 2.3): first scale from the maxima, bar
       // matrices, one INT8 GEMM reduced to row/column maxima, exponents.
@@ -483,6 +499,19 @@ int run_complex(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const 
     k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
         (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
         (double*)(ws + L.SB), (int*)(ws + L.status));
+    if (mode == OZ2_MODE_EXACT) {
+      k1_partials_strided_cplx<T, true><<<gA, 256, 0, g_stream>>>(
+          A, lda, m, k, L.nch, (double*)(ws + L.partA), nullptr, (const int32_t*)(ws + L.eA));
+      k1_partials_contig<T, true><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
+          B, 2 * ldb, n, 2 * k, L.nch, (double*)(ws + L.partB), nullptr,
+          (const int32_t*)(ws + L.eB));
+      k1_fold_rescale<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partA), L.nch, m, tab, (int32_t*)(ws + L.eA), (double*)(ws + L.SA),
+          (int*)(ws + L.status));
+      k1_fold_rescale<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
+          (double*)(ws + L.partB), L.nch, n, tab, (int32_t*)(ws + L.eB), (double*)(ws + L.SB),
+          (int*)(ws + L.status));
+    }
   }
   clk.mark(1);
   // K2: integers and the residues of the three components.
@@ -571,7 +600,7 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
   if (bad) *bad = -1;
   if (batch < 0) return -1;
   if (batch > 0 && !P) return -2;
-  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL) return -3;
+  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL) return -3;   // fast modes only
   if (batch > 65535) return OZ2_ERR_TOO_LARGE;
   for (int i = 0; i < batch; ++i) {
     const oz2_problem& q = P[i];

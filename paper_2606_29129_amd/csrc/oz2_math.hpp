@@ -102,6 +102,21 @@ OZ2_HD int alg2_exponent(double S, float p_prop) {
   return (int)floor((double)w - (double)t);            // exact difference
 }
 
+// Exact mode (an optional variant of Algorithm 2): the largest e with
+// 2^(2e+1) S <= P - 1 for a finite S > 0.  S 2^(2e+1) is a binary64 value
+// near P (no overflow or underflow), and a binary64 x satisfies x <= P - 1
+// exactly when x <= RD64(P - 1) = pm1_rd, so the comparison is exact.  With
+// S in [2^ES, 2^(ES+1)) and pm1_rd in [2^EQ, 2^(EQ+1)) the answer lies in
+// [floor((EQ - ES) / 2) - 1, floor((EQ - ES) / 2)].  S = 0 gives 0.
+OZ2_HD int emax_exponent(double S, double pm1_rd) {
+  if (S == 0.0) return 0;
+  double f;
+  const int ES = split_pow2(S, &f), EQ = split_pow2(pm1_rd, &f);
+  int e = (EQ - ES) >> 1;   // floor division (arithmetic shift)
+  if (ldexp(S, 2 * e + 1) > pm1_rd) --e;
+  return e;
+}
+
 // Algorithm 1 (Section 2.3): the original fast-mode exponent.
 //   t = RU32(delta * RU32(log2f(S/2^s) + s));
 //   return floor(P'_fast - max(1, t)) - floor(log2 amax).

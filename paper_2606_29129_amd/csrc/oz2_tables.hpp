@@ -32,6 +32,7 @@ struct ModTable {
   double H[kMaxSlices];            // P/2 in 39-bit slices
   double invP;                     // RN(1/P), only for quotient estimates
   double quarterP;                 // a binary64 value a little below P/4
+  double pm1_rd;                   // RD64(P - 1): x <= P - 1 iff x <= pm1_rd (binary64 x)
   float p_prop;                    // P'_prop = RD32(log2(P-1)/2 - 0.5)
   float p_fast;                    // P'_fast = RD32(log2(P-1)/2 - 1.5)
   float delta;                     // RU32(0.5 / (1 - 4 u32))
@@ -177,6 +178,13 @@ inline bool build_table(int N, bool accurate_limbs, ModTable* T) {
   T->log2P = (double)log2P;
   T->invP = (double)exp2l(-log2P);
   T->quarterP = (double)(exp2l(log2P - 2.0L) * (1.0L - 0x1p-30L));
+  {
+    // P - 1 rounded down to binary64: its top 53 bits, truncated.
+    const Big Pm1 = P.sub_small(1);
+    const int bl = Pm1.bitlen();
+    const int sh = bl > 53 ? bl - 53 : 0;
+    T->pm1_rd = ldexp((double)Pm1.bits(sh, 53), sh);
+  }
   long double log2Pm1 = P.sub_small(1).log2l_approx();
   if (!round_f32_checked(log2Pm1 / 2 - 0.5L, false, &T->p_prop)) return false;
   if (!round_f32_checked(log2Pm1 / 2 - 1.5L, false, &T->p_fast)) return false;

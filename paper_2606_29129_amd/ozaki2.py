@@ -18,8 +18,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libozaki2.so")
 
-MODE_REVISED, MODE_ORIGINAL, MODE_ACCURATE = 0, 1, 2
-_MODES = {"revised": 0, "original": 1, "fast": 1, "accurate": 2}
+MODE_REVISED, MODE_ORIGINAL, MODE_ACCURATE, MODE_EXACT = 0, 1, 2, 3
+_MODES = {"revised": 0, "original": 1, "fast": 1, "accurate": 2, "exact": 3}
 NUM_STAGES = 5
 STAGE_NAMES = ("norms_exponents", "convert_split", "int8_gemm", "crt_unscale", "other")
 

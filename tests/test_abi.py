@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol():
     ((4, 4, 4, 1, 4, 1, 4, 1, 3, 14, 0), -9),
     ((4, 4, 4, 1, 4, 1, 4, 1, 4, 1, 0), -10),
     ((4, 4, 4, 1, 4, 1, 4, 1, 4, 21, 0), -10),
-    ((4, 4, 4, 1, 4, 1, 4, 1, 4, 14, 3), -11),
+    ((4, 4, 4, 1, 4, 1, 4, 1, 4, 14, 4), -11),
     ((4, 4, 2**22 + 1, 1, 4, 1, 2**22 + 1, 1, 4, 14, 0), 1),    # OZ2_K_MAX
     ((4, 4, 2**18 + 1, 1, 4, 1, 2**18 + 1, 1, 4, 14, 2), 1),    # accurate mode
 ])
@@ -124,7 +124,7 @@ def test_k_limits_of_the_header():
     ((-1, 1, 1, 16, 1, 16, 1, 16, 1, 14, 0), -1),
     ((4, 4, 4, 16, 3, 16, 4, 16, 4, 14, 0), -5),
     ((4, 4, 4, 16, 4, 16, 4, 16, 4, 21, 0), -10),
-    ((4, 4, 4, 16, 4, 16, 4, 16, 4, 14, 3), -11),
+    ((4, 4, 4, 16, 4, 16, 4, 16, 4, 14, 4), -11),
     ((4, 4, 4, 16, 4, 16, 4, 16, 4, 14, 2), 4),     # accurate mode: unsupported
     ((4, 4, 4, 24, 4, 16, 4, 16, 4, 14, 0), -4),    # A not aligned to a complex entry
     ((4, 4, 4, 16, 4, 40, 4, 16, 4, 14, 0), -6),

@@ -73,6 +73,8 @@ def test_batched_argument_errors():
     assert rc == -5 and bad == 1
     rc, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=2)
     assert rc == -3
+    rc, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=3)
+    assert rc == -3
 
 
 def test_batched_nonfinite_row_sets_status_and_nan_row():

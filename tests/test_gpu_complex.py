@@ -217,3 +217,14 @@ def test_full_size_componentwise_bound(full_complex):
         bad = int(((d.real.abs() > bound) | (d.imag.abs() > bound)).sum())
         assert bad == 0, f"{bad} entries of rows {r0}..{r0 + 2047} outside the bound"
         del Cn, bound, d, absA
+
+
+def test_zgemm_exact_mode_with_huge_rows():
+    """Exact mode on complex inputs, rows and columns beyond 1e154 included:
+    bit for bit with the oracle (the fallback pass of the complex row kernel
+    and of the component view of B)."""
+    A, B = inputs.complex_problem(40, 33, 90, 1.0, seed=64)
+    A[5] *= 2.0 ** 700
+    B[:, 8] *= 2.0 ** 650
+    r = zref.gemm(A, B, 16, 3)
+    assert _same(_gpu(A, B, 16, mode=3), r["C"])

@@ -343,3 +343,85 @@ def test_k_beyond_one_int32_block(m, n, k, N, mode):
     rc = oz.ozaki2_debug_stages(m, n, k, Ad, lda, Bd, ldb, N, mode, 0,
                                 None, None, None, None, None, None, Ct)
     assert rc == 4   # OZ2_ERR_UNSUPPORTED
+
+
+# --- exact mode (OZ2_MODE_EXACT = 3) -------------------------------------------
+
+@pytest.mark.parametrize("m,n,k,phi,N,seed", [(300, 280, 520, 1.0, 14, 51), (37, 301, 129, 2.0, 20, 52),
+                                              (70, 33, 65, 4.0, 8, 53)])
+def test_exact_mode_stage_parity(m, n, k, phi, N, seed):
+    """Exact mode: squared norms, exponents (the exact maximum), residues,
+    INT32 products and C equal the oracle bit for bit."""
+    print(f"case exact m={m} n={n} k={k} N={N}", flush=True)
+    A, B = inputs.problem(m, n, k, phi, seed)
+    r = ref.gemm(A, B, N, ref.EXACT)
+    g = _gpu_stages(A, B, N, 3, N - 1)
+    assert _bits_equal(g["SA"], np.array(r["SA"])) and _bits_equal(g["SB"], np.array(r["SB"]))
+    assert list(g["eA"]) == r["e_rows"] and list(g["eB"]) == r["e_cols"]
+    for t in (0, N - 1):
+        assert np.array_equal(g["RA"][t], r["RA"][t])
+        assert np.array_equal(g["RB"][t], r["RB"][t].T)
+    assert np.array_equal(g["Ct"].astype(np.int64), r["G"][N - 1])
+    assert _bits_equal(_gpu_dgemm(A, B, N, mode=3), r["C"])
+
+
+def test_exact_mode_huge_rows_and_columns():
+    """Rows and columns beyond 1e154 (their squared norms overflow binary64):
+    the fallback pass gives the oracle's exponents, norms (of the scaled-down
+    entries) and C bit for bit, with no status bit; the revised mode returns
+    NaN for them."""
+    A, B = inputs.problem(40, 30, 150, 1.0, seed=61)
+    A[3] *= 2.0 ** 700
+    A[7, ::3] *= 2.0 ** 900
+    A[9] *= 2.0 ** -700                   # tiny row alongside
+    B[:, 4] *= 2.0 ** 600
+    B[::7, 11] *= 2.0 ** 1000
+    N = 16
+    r = ref.gemm(A, B, N, ref.EXACT)
+    g = _gpu_stages(A, B, N, 3, 0)
+    assert list(g["eA"]) == r["e_rows"] and list(g["eB"]) == r["e_cols"]
+    assert _bits_equal(g["SA"], np.array(r["SA"])) and _bits_equal(g["SB"], np.array(r["SB"]))
+    oz.ozaki2_get_device_status()        # clear
+    C = _gpu_dgemm(A, B, N, mode=3)
+    assert _bits_equal(C, r["C"])
+    assert oz.ozaki2_get_device_status() == 0
+    Cr = _gpu_dgemm(A, B, N, mode=0)
+    assert np.isnan(Cr[3]).all() and np.isnan(Cr[:, 4]).all()
+
+
+def test_exact_mode_is_scale_invariant_bit_for_bit():
+    """A -> 2^+-300 A scales C exactly in every row in exact mode (the
+    exponent is the exact maximum); 4096 rows include ones where Algorithm
+    2's binary32 rounding of w lowers the exponent at this scale."""
+    A, B = inputs.problem(512, 64, 256, 0.5, seed=0)
+    C0 = _gpu_dgemm(A, B, 14, mode=3)
+    for s in (300, -300):
+        Cs = _gpu_dgemm(A * 2.0 ** s, B, 14, mode=3)
+        assert _bits_equal(Cs, C0 * 2.0 ** s)
+
+
+def test_exact_mode_infinite_entry_is_flagged():
+    A, B = inputs.problem(20, 10, 40, 1.0, seed=62)
+    A[2, 5] = np.inf
+    A[4] *= 2.0 ** 800
+    C = _gpu_dgemm(A, B, 14, mode=3)
+    assert np.isnan(C[2]).all() and np.isfinite(np.delete(C, 2, axis=0)).all()
+    assert oz.ozaki2_get_device_status() & 1
+    rows = [i for i in range(20) if i != 2]
+    assert _bits_equal(C[rows], ref.gemm(A[rows], B, 14, ref.EXACT)["C"])
+
+
+def test_exact_mode_sgemm_parity():
+    A, B = inputs.problem(70, 90, 150, 1.0, seed=63)
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    want = ref.sgemm(A32, B32, 7, ref.EXACT)
+    m, k = A32.shape
+    n = B32.shape[1]
+    Ad, lda = _colmajor(A32)
+    Bd, ldb = _colmajor(B32)
+    Cd = torch.zeros((n, m), dtype=torch.float32, device=DEV)
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    assert oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, 7, 3) == 0
+    torch.cuda.synchronize()
+    got = Cd.cpu().numpy().T.copy()
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
