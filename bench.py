@@ -87,6 +87,10 @@ def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0):
         Si, Sj = scaling.norm_sq_ru(row), scaling.norm_sq_ru(col)
         if mode == 0:
             ei, fj = scaling.alg2_log2_mu(Si, pp), scaling.alg2_log2_mu(Sj, pp)
+        elif mode == 3:
+            _, P, _, _ = constants.step1(N)
+            ei = scaling.exact_mode_log2_mu(row, P)[0]
+            fj = scaling.exact_mode_log2_mu(col, P)[0]
         else:
             ei = scaling.alg1_log2_mu(Si, float(np.max(np.abs(row))), pf, d)
             fj = scaling.alg1_log2_mu(Sj, float(np.max(np.abs(col))), pf, d)
@@ -309,7 +313,8 @@ def main():
     ap.add_argument("--N", type=int, default=14)
     ap.add_argument("--phi", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="revised", choices=["revised", "original", "accurate"])
+    ap.add_argument("--mode", default="revised",
+                    choices=["revised", "original", "accurate", "exact"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-native", action="store_true")
@@ -338,7 +343,7 @@ def main():
     m = args.m or args.size
     n = args.n or args.size
     k = args.k or args.size
-    N, mode = args.N, {"revised": 0, "original": 1, "accurate": 2}[args.mode]
+    N, mode = args.N, {"revised": 0, "original": 1, "accurate": 2, "exact": 3}[args.mode]
     if mode == 2 and not args.no_cpu_baseline:
         # the oracle's accurate-mode exponents need the whole bar product
         _log("accurate mode: no sampled CPU oracle leg")

@@ -20,7 +20,8 @@ Every result is one JSON line on stdout.
 * ``scale``: A multiplied by 2^300, 2^-300 (C must be the unscaled result
   times the same power, bit for bit, in every row whose Algorithm 2 exponent
   shifted exactly; rows where the binary32 rounding of w lowered it by one
-  are counted) and by 3.7e100, 3.7e-100 (error).
+  are counted; the exact mode must shift every row and scale all of C) and
+  by 3.7e100, 3.7e-100 (error).
 * ``accuracy``: m = n = k = 8192, phi = 2; DGEMM for N = 8..20 and SGEMM on
   the binary32-rounded inputs for N = 5..9: maximum relative and
   componentwise error on a block of rows and columns picked by a seeded
@@ -342,6 +343,21 @@ def sweep_scale(args):
         out.update(sample=f"{args.sample}x{args.sample} block",
                    **errors(P.C_block(rows, cols), ref, absAB))
         _emit(out)
+        if label.startswith("2^"):
+            # exact mode: the exact maximal exponent shifts by exactly -+300
+            # in every row, so C scales exactly everywhere
+            P.run(N, 3)
+            torch.cuda.synchronize()
+            Cx = P.C_cm.clone()
+            e1, _ = P.exponents(N, 3)
+            P.release()
+            P = Problem(torch, A, B, N, mode=3)
+            P.run(N, 3)
+            torch.cuda.synchronize()
+            e0x, _ = P.exponents(N, 3)
+            _emit(dict(leg="scale", m=S, n=S, k=S, phi=phi, N=N, factor=label, mode="exact",
+                       rows_exponent_shifted_exactly=int((e1 == e0x + sh).sum()),
+                       bit_identical_to_scaled=bool(torch.equal(Cx, P.C_cm * c))))
         P.release()
         del Ac
 
