@@ -153,8 +153,10 @@ def fixed_error_leg(A_rm, B_rm, A_cm, B_cm, m, n, k, mode, target, stream, seed,
 
 def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
     """256 independent DGEMMs, m, n, k log-uniform in [64, 2048], phi uniform
-    in [0.5, 3], N per problem from the autotuner for the target max relative
-    error; one graph launch per batch versus one ozaki2_dgemm call per
+    in [0.5, 3], N per problem from the library's autotuner for the target max
+    relative error (one call with N = 0; the timed calls replay the graph with
+    the N it chose, and calls that re-run the autotuner every time are timed
+    separately); one graph launch per batch versus one ozaki2_dgemm call per
     problem."""
     import numpy as np
     import torch
@@ -165,19 +167,26 @@ def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
     rng = np.random.default_rng(seed)
     shapes = np.exp(rng.uniform(np.log(64), np.log(2048), (count, 3))).round().astype(int)
     phis = rng.uniform(0.5, 3.0, count)
-    pairs, Ns, flops = [], [], 0.0
+    pairs, flops = [], 0.0
     for i in range(count):
         m, n, k = (int(x) for x in shapes[i])
         A = inputs.ozaki_matrix_torch(m, k, float(phis[i]), seed + i, 0, dev)
         B = inputs.ozaki_matrix_torch(k, n, float(phis[i]), seed + i, 1, dev)
-        phi_hat = max(autotune.estimate_phi(A), autotune.estimate_phi(B))
-        Ns.append(autotune.pick_N(k, phi_hat, target))
         pairs.append((A, B))
         flops += 2.0 * m * n * k
     stream = torch.cuda.current_stream()
+    # N per problem from the library's autotuner (N = 0 with the target),
+    # compared with the Python autotuner's pick for the same data
+    _, Ns = oz.dgemm_batched(pairs, 0, target=target, return_N=True)
+    torch.cuda.synchronize()
+    py_Ns = [autotune.pick_N(A.shape[1], max(autotune.estimate_phi(A), autotune.estimate_phi(B)),
+                             target) for A, B in pairs]
 
     def run_batched():
         return oz.dgemm_batched(pairs, Ns)
+
+    def run_autotuned():
+        return oz.dgemm_batched(pairs, 0, target=target)
 
     def run_plain():
         return [oz.dgemm(A, B, N=N) for (A, B), N in zip(pairs, Ns)]
@@ -195,6 +204,7 @@ def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
         return e0.elapsed_time(e1) / steps, out
 
     ms_b, outs = timed(run_batched)
+    ms_auto, _ = timed(run_autotuned)
     ms_p, outs_p = timed(run_plain)
     same = all(torch.equal(a.view(torch.int64), b.view(torch.int64)) for a, b in zip(outs, outs_p))
     # accuracy on sampled entries of a few problems, against the exact product
@@ -214,6 +224,9 @@ def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
                 ms_plain=round(ms_p, 4), tflops_plain=round(flops / ms_p / 1e9, 2),
                 speedup=round(ms_p / ms_b, 2), bit_identical_to_plain=bool(same),
                 N_histogram=hist, max_rel_err_sampled=max_rel,
+                N_source="library autotuner (ozaki2_dgemm_batched with N = 0 and the target)",
+                N_agrees_with_python_autotuner=int(sum(a == b for a, b in zip(Ns, py_Ns))),
+                ms_batched_autotune_every_call=round(ms_auto, 4),
                 sampled="16 entries of each of %d problems vs the exact product" % check)
 
 

@@ -248,7 +248,9 @@ int ozaki2_get_tile(int64_t m, int64_t n, int64_t k, int N, int* tile);
 
 /*
  * Batched emulated DGEMM.  One problem of a batch, column-major as for
- * ozaki2_dgemm; N is its number of moduli (OZ2_N_MIN..OZ2_N_MAX).
+ * ozaki2_dgemm.  N is its number of moduli (OZ2_N_MIN..OZ2_N_MAX), or 0 to
+ * let the library pick it for the batch's accuracy target; N_used is
+ * written by ozaki2_dgemm_batched (its input value is ignored).
  */
 typedef struct oz2_problem {
   int64_t m, n, k;
@@ -259,7 +261,7 @@ typedef struct oz2_problem {
   double* C;
   int64_t ldc;
   int N;
-  int reserved; /* must be 0 */
+  int N_used;   /* output: the number of moduli used (0 if nothing was computed) */
 } oz2_problem;
 
 /*
@@ -267,22 +269,55 @@ typedef struct oz2_problem {
  * any shapes and moduli counts (problems[] is a HOST array; the matrices are
  * device memory), with mode OZ2_MODE_REVISED or OZ2_MODE_ORIGINAL.
  *
+ * Problems with N = 0 get the smallest N whose calibrated maximum relative
+ * error (the library's autotuner, see ozaki2_autotune_N) is at most
+ * target_max_rel_err / 4 for their k and for phi estimated from their data
+ * (ozaki2_estimate_phi of A and of B, the larger of the two); this reads the
+ * operands once more and synchronises the stream before the launch.  The
+ * target is ignored when every N is given.
+ *
  * All problems are computed by one HIP graph launch: the stages of
  * ozaki2_dgemm run once for the whole batch (one grid per stage) and the
  * INT8 GEMMs of every problem and modulus run in one persistent kernel over
- * a shared work list.  k <= OZ2_K_BLOCK per problem.  The graph is built on the first call
- * with a given batch signature (shapes, N, mode, workspace) and replayed
- * afterwards; only the matrix pointers are refreshed per call (a small host
- * -> device copy inside the graph).  Results are bit-identical to calling
- * ozaki2_dgemm on each problem.
+ * a shared work list.  k <= OZ2_K_BLOCK per problem.  The graph is built on
+ * the first call with a given batch signature (shapes, N, mode, workspace)
+ * and replayed afterwards; only the matrix pointers are refreshed per call
+ * (a small host -> device copy inside the graph).  Results are bit-identical
+ * to calling ozaki2_dgemm on each problem with its N_used.
  *
  * Returns 0; -1 if batch < 0; -2 if problems is NULL with batch > 0; -3 for
- * an unsupported mode; or, for the first invalid problem, the code
- * ozaki2_dgemm would return for it, with its index in *bad_index (may be
- * NULL).  Nothing is launched on error.
+ * an unsupported mode; -4 if some N is 0 and the target is not in (0, 1];
+ * or, for the first invalid problem, the code ozaki2_dgemm would return for
+ * it, with its index in *bad_index (may be NULL).  Nothing is launched on
+ * error.
  */
-int ozaki2_dgemm_batched(int batch, const oz2_problem* problems, int mode,
-                         int* bad_index);
+int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode,
+                         double target_max_rel_err, int* bad_index);
+
+/*
+ * The autotuner.  The error of the emulated product is set by the number of
+ * moduli (wider integers) and the spread of the entry magnitudes; for the
+ * distribution of the paper's experiments, (rand - 0.5) exp(phi randn)
+ * (Section 3.2), log|a| has variance 1 + phi^2.  The library carries a
+ * table of maximum relative errors of ozaki2_dgemm measured on the GPU
+ * against exact products, per (k, phi, N) grid point (k 64..16384, phi
+ * 0.5..4, N 10..20).
+ *
+ * ozaki2_autotune_N -- host only: *N = the smallest N whose tabulated error
+ * at the next grid point at or above (k, phi) is at most target / 4 (20 if
+ * none is).  Returns 0; -1 k < 0; -2 phi not >= 0; -3 target not in (0, 1];
+ * -4 N is NULL.
+ *
+ * ozaki2_estimate_phi -- phi of a column-major rows x cols binary64 device
+ * matrix (leading dimension ld): sqrt(max(var - 1, 0)) with var the unbiased
+ * sample variance of log|x| over its first min(rows cols, 2^20) entries in
+ * storage order, zeros and non-finite entries skipped (0 with fewer than two
+ * such entries).  Synchronises the stream.  Returns 0; -1..-5 for the
+ * argument in that position; or OZ2_ERR_HIP.
+ */
+int ozaki2_autotune_N(int64_t k, double phi, double target_max_rel_err, int* N);
+int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld,
+                        double* phi);
 
 /*
  * ozaki2_debug_stages -- run Steps 1-3 of ozaki2_dgemm for binary64 A, B

@@ -116,6 +116,56 @@ def pick_N(k: int, phi: float, target: float, table=None, margin: float = 4.0) -
     return 20
 
 
+HEADER = os.path.join(HERE, "csrc", "oz2_autotune_table.hpp")
+
+
+def header_text(table=None) -> str:
+    """The calibrated table as a C++ header for the library's own N choice
+    (``ozaki2_autotune_N``, and N = 0 in ``ozaki2_dgemm_batched``): the k and
+    phi grid points, the N range and the max relative errors, each printed
+    with repr (the shortest string that reads back to the same binary64)."""
+    t = table or load_table()
+    ks = sorted(int(x) for x in t["errors"].keys())
+    phis = sorted(float(x) for x in t["errors"][str(ks[0])].keys())
+    Ns = sorted(int(x) for x in t["errors"][str(ks[0])][str(phis[0])].keys())
+    assert Ns == list(range(Ns[0], Ns[-1] + 1))
+    lines = [
+        "// oz2_autotune_table.hpp -- generated by paper_2606_29129_amd/autotune.py",
+        "// (header_text) from autotune_table.json: the maximum relative error of",
+        "// ozaki2_dgemm measured against exact products of sampled entries, per",
+        "// grid point (k, phi) of the input distribution (rand - 0.5) exp(phi randn)",
+        f"// and number of moduli N (m = {t.get('m')}, {t.get('block')}x{t.get('block')} sampled"
+        f" blocks, seed {t.get('seed')}).",
+        "#pragma once",
+        "",
+        "namespace oz2 {",
+        "",
+        f"constexpr int kTuneNK = {len(ks)}, kTuneNPhi = {len(phis)}, kTuneN0 = {Ns[0]}, "
+        f"kTuneNN = {len(Ns)};",
+        "constexpr long long kTuneK[kTuneNK] = {" + ", ".join(str(k) for k in ks) + "};",
+        "constexpr double kTunePhi[kTuneNPhi] = {" + ", ".join(repr(p) for p in phis) + "};",
+        "constexpr double kTuneErr[kTuneNK][kTuneNPhi][kTuneNN] = {",
+    ]
+    for k in ks:
+        lines.append("  {")
+        for p in phis:
+            row = t["errors"][str(k)][str(p)]
+            lines.append("    {" + ", ".join(repr(float(row[str(N)])) for N in Ns) + "},")
+        lines.append("  },")
+    lines += ["};", "", "}  // namespace oz2", ""]
+    return "\n".join(lines)
+
+
+def write_header(path: str = HEADER, table=None) -> bool:
+    """Write the header if its content changed; True if written."""
+    text = header_text(table)
+    if os.path.exists(path) and open(path).read() == text:
+        return False
+    with open(path, "w") as f:
+        f.write(text)
+    return True
+
+
 def calibrate(m: int = 256, block: int = 32, seed: int = 7, path: str = TABLE, log=print):
     """Measure max relative errors on the GPU for the (k, phi, N) grid and
     write the table.  Needs a GPU."""

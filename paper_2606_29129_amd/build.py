@@ -27,7 +27,12 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/oz2_lib.hip into libozaki2.so next to this file."""
+    """Compile csrc/oz2_lib.hip into libozaki2.so next to this file (after
+    regenerating the autotuner's table header from autotune_table.json)."""
+    sys.path.insert(0, ROOT)
+    from paper_2606_29129_amd import autotune
+    if autotune.write_header() and verbose:
+        print("regenerated", autotune.HEADER, flush=True)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "oz2_lib.hip"), "-o", tmp]

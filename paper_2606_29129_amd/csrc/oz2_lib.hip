@@ -18,6 +18,7 @@
 #include "oz2_tables.hpp"
 #include "oz2_batched.hpp"
 #include "oz2_complex.hpp"
+#include "oz2_autotune.hpp"
 
 #include <algorithm>
 
@@ -36,6 +37,8 @@ struct DevState {
   ModTable* d_tables = nullptr;  // device address of g_tables
   void* ws = nullptr;            // library-owned workspace
   size_t ws_bytes = 0;
+  void* tune = nullptr;          // autotuner: operand descriptors and partial statistics
+  size_t tune_bytes = 0;
 };
 
 DevState g_dev[kMaxDevices];
@@ -596,7 +599,48 @@ void batch_release() {
   g_batch.valid = false;
 }
 
-int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
+// phi of each operand (sample variance of log|x|, oz2_autotune.hpp): one
+// launch for all of them on the library stream, then a synchronising copy
+// of the per-block partials.
+int estimate_phis(int dev, const std::vector<StatSrc>& srcs, std::vector<double>* phis) {
+  const size_t ns = srcs.size();
+  phis->assign(ns, 0.0);
+  if (ns == 0) return 0;
+  DevState& D = g_dev[dev];
+  const size_t off_part = align256(sizeof(StatSrc) * ns);
+  const size_t need = off_part + sizeof(double) * 3 * kStatBlocks * ns;
+  if (D.tune_bytes < need) {
+    if (D.tune) {
+      if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
+      (void)hipFree(D.tune);
+    }
+    D.tune = nullptr;
+    D.tune_bytes = 0;
+    if (hipMalloc(&D.tune, need) != hipSuccess) return OZ2_ERR_WORKSPACE;
+    D.tune_bytes = need;
+  }
+  char* base = reinterpret_cast<char*>(D.tune);
+  std::vector<double> part(3 * kStatBlocks * ns);
+  if (hipMemcpyAsync(base, srcs.data(), sizeof(StatSrc) * ns, hipMemcpyHostToDevice, g_stream) !=
+      hipSuccess)
+    return OZ2_ERR_HIP;
+  k_logstats<<<(unsigned)(ns * kStatBlocks), 256, 0, g_stream>>>(
+      reinterpret_cast<const StatSrc*>(base), reinterpret_cast<double*>(base + off_part));
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(part.data(), base + off_part, sizeof(double) * part.size(),
+                     hipMemcpyDeviceToHost, g_stream) != hipSuccess ||
+      hipStreamSynchronize(g_stream) != hipSuccess)
+    return OZ2_ERR_HIP;
+  for (size_t i = 0; i < ns; ++i) (*phis)[i] = phi_from_partials(part.data() + 3 * kStatBlocks * i);
+  return 0;
+}
+
+StatSrc stat_src(const double* X, int64_t rows, int64_t cols, int64_t ld) {
+  return StatSrc{X, rows > 0 ? rows : 1, ld, std::min<int64_t>(rows * cols, kPhiSample)};
+}
+
+// Batched path with every N given (1..20).
+int run_batched_resolved(int batch, const oz2_problem* P, int mode, int* bad) {
   if (bad) *bad = -1;
   if (batch < 0) return -1;
   if (batch > 0 && !P) return -2;
@@ -605,7 +649,6 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
   for (int i = 0; i < batch; ++i) {
     const oz2_problem& q = P[i];
     int rc = check_args(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, q.N, mode, true);
-    if (!rc && q.reserved != 0) rc = -12;
     if (!rc && q.k > OZ2_K_BLOCK) rc = OZ2_ERR_K_TOO_LARGE;  // no k blocking in a batch
     if (!rc && (q.m > 65535 * (int64_t)kBatchTile || q.n > 65535 * (int64_t)kBatchTile))
       rc = OZ2_ERR_TOO_LARGE;
@@ -826,8 +869,79 @@ int run_batched(int batch, const oz2_problem* P, int mode, int* bad) {
 
 extern "C" {
 
-int ozaki2_dgemm_batched(int batch, const oz2_problem* problems, int mode, int* bad_index) {
-  return run_batched(batch, problems, mode, bad_index);
+int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode, double target_max_rel_err,
+                         int* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (batch < 0) return -1;
+  if (batch > 0 && !problems) return -2;
+  if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL) return -3;
+  bool any_auto = false;
+  for (int i = 0; i < batch; ++i) any_auto |= problems[i].N == 0;
+  if (any_auto && !(target_max_rel_err > 0.0 && target_max_rel_err <= 1.0)) return -4;
+  // Validate with a placeholder N for the problems that leave N to the
+  // library, so that nothing is launched for an invalid batch.
+  std::vector<oz2_problem> Q(problems, problems + batch);
+  for (auto& q : Q)
+    if (q.N == 0) q.N = OZ2_N_MAX;
+  for (int i = 0; i < batch; ++i) {
+    const oz2_problem& q = Q[i];
+    int rc = check_args(q.m, q.n, q.k, q.A, q.lda, q.B, q.ldb, q.C, q.ldc, q.N, mode, true);
+    if (!rc && q.k > OZ2_K_BLOCK) rc = OZ2_ERR_K_TOO_LARGE;
+    if (rc) {
+      if (bad_index) *bad_index = i;
+      return rc;
+    }
+  }
+  if (any_auto) {
+    std::vector<StatSrc> srcs;
+    std::vector<int> who;
+    for (int i = 0; i < batch; ++i) {
+      const oz2_problem& q = problems[i];
+      if (q.N != 0 || q.m == 0 || q.n == 0 || q.k == 0) continue;
+      srcs.push_back(stat_src(q.A, q.m, q.k, q.lda));
+      srcs.push_back(stat_src(q.B, q.k, q.n, q.ldb));
+      who.push_back(i);
+    }
+    if (!who.empty()) {
+      int dev, rc;
+      if ((rc = ensure_device(&dev))) return rc;
+      std::vector<double> phis;
+      if ((rc = estimate_phis(dev, srcs, &phis))) return rc;
+      for (size_t w = 0; w < who.size(); ++w)
+        Q[who[w]].N = tune_pick_N(Q[who[w]].k, std::max(phis[2 * w], phis[2 * w + 1]),
+                                  target_max_rel_err);
+    }
+  }
+  for (int i = 0; i < batch; ++i) {
+    const oz2_problem& q = problems[i];
+    problems[i].N_used = (q.N == 0 && (q.m == 0 || q.n == 0 || q.k == 0)) ? 0 : Q[i].N;
+  }
+  return run_batched_resolved(batch, Q.data(), mode, bad_index);
+}
+
+int ozaki2_autotune_N(int64_t k, double phi, double target_max_rel_err, int* N) {
+  if (k < 0) return -1;
+  if (!(phi >= 0.0 && phi <= 1e300)) return -2;
+  if (!(target_max_rel_err > 0.0 && target_max_rel_err <= 1.0)) return -3;
+  if (!N) return -4;
+  *N = tune_pick_N(k, phi, target_max_rel_err);
+  return 0;
+}
+
+int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld, double* phi) {
+  if (rows < 0) return -1;
+  if (cols < 0) return -2;
+  if (!X && rows > 0 && cols > 0) return -3;
+  if (ld < (rows > 1 ? rows : 1)) return -4;
+  if (!phi) return -5;
+  *phi = 0.0;
+  if (rows == 0 || cols == 0) return 0;
+  int dev, rc;
+  if ((rc = ensure_device(&dev))) return rc;
+  std::vector<double> phis;
+  if ((rc = estimate_phis(dev, {stat_src(X, rows, cols, ld)}, &phis))) return rc;
+  *phi = phis[0];
+  return 0;
 }
 
 
@@ -944,6 +1058,7 @@ int ozaki2_finalize(void) {
     if (hipSetDevice(d) != hipSuccess) continue;
     (void)hipDeviceSynchronize();
     if (D.ws) (void)hipFree(D.ws);
+    if (D.tune) (void)hipFree(D.tune);
     D = DevState();
   }
   return 0;

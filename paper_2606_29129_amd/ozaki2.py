@@ -32,7 +32,7 @@ class Oz2Problem(ctypes.Structure):
     """struct oz2_problem of include/ozaki2.h."""
     _fields_ = [("m", _c_i64), ("n", _c_i64), ("k", _c_i64), ("A", _vp), ("lda", _c_i64),
                 ("B", _vp), ("ldb", _c_i64), ("C", _vp), ("ldc", _c_i64), ("N", _c_int),
-                ("reserved", _c_int)]
+                ("N_used", _c_int)]
 
 _SIGS = {
     "ozaki2_dgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
@@ -58,8 +58,10 @@ _SIGS = {
     "ozaki2_debug_stages": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _c_int, _c_int, _c_int]
                             + [_vp] * 7, _c_int),
     "ozaki2_debug_log2f": ([_vp, _vp, _c_i64], _c_int),
-    "ozaki2_dgemm_batched": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int, ctypes.POINTER(_c_int)],
-                             _c_int),
+    "ozaki2_dgemm_batched": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int, ctypes.c_double,
+                              ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_autotune_N": ([_c_i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_estimate_phi": ([_c_i64, _c_i64, _vp, _c_i64, ctypes.POINTER(ctypes.c_double)], _c_int),
 }
 
 
@@ -203,9 +205,10 @@ def ozaki2_debug_stages(m, n, k, A, lda, B, ldb, N, mode, t,
                                      _ptr(RB), _ptr(Ct))
 
 
-def ozaki2_dgemm_batched(problems, mode=MODE_REVISED):
-    """problems: a sequence of Oz2Problem (or of tuples with its fields, pointers
-    as tensors or ints).  Returns (rc, bad_index)."""
+def ozaki2_dgemm_batched(problems, mode=MODE_REVISED, target=0.0):
+    """problems: a sequence of Oz2Problem (or of tuples with its fields up to
+    N, pointers as tensors or ints; N = 0 lets the library pick N for the
+    target).  Returns (rc, bad_index, [N_used per problem])."""
     arr = (Oz2Problem * max(1, len(problems)))()
     for i, q in enumerate(problems):
         if isinstance(q, Oz2Problem):
@@ -214,8 +217,22 @@ def ozaki2_dgemm_batched(problems, mode=MODE_REVISED):
             m, n, k, A, lda, B, ldb, C, ldc, N = q
             arr[i] = Oz2Problem(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, 0)
     bad = ctypes.c_int(-1)
-    rc = lib().ozaki2_dgemm_batched(len(problems), arr, mode, ctypes.byref(bad))
-    return rc, bad.value
+    rc = lib().ozaki2_dgemm_batched(len(problems), arr, mode, float(target), ctypes.byref(bad))
+    return rc, bad.value, [arr[i].N_used for i in range(len(problems))]
+
+
+def ozaki2_autotune_N(k, phi, target):
+    N = ctypes.c_int(0)
+    _check("ozaki2_autotune_N", lib().ozaki2_autotune_N(k, float(phi), float(target),
+                                                          ctypes.byref(N)))
+    return N.value
+
+
+def ozaki2_estimate_phi(rows, cols, X, ld):
+    phi = ctypes.c_double(0.0)
+    _check("ozaki2_estimate_phi", lib().ozaki2_estimate_phi(rows, cols, _ptr(X), ld,
+                                                              ctypes.byref(phi)))
+    return phi.value
 
 
 def ozaki2_debug_log2f(x, y, n):
@@ -284,9 +301,11 @@ def _gemm(A, B, N, mode, out, fn):
     return C
 
 
-def dgemm_batched(pairs, N, mode="revised"):
+def dgemm_batched(pairs, N=0, mode="revised", target=None, return_N=False):
     """C_i = A_i @ B_i for a list of row-major float64 CUDA tensor pairs, in one
-    batched call; N is an int or a list with one moduli count per problem."""
+    batched call.  N is an int or a list with one moduli count per problem;
+    0 lets the library pick N for the max relative error ``target``.  With
+    ``return_N`` also returns the N used per problem."""
     import torch
     Ns = [N] * len(pairs) if isinstance(N, int) else list(N)
     outs, probs = [], []
@@ -300,7 +319,8 @@ def dgemm_batched(pairs, N, mode="revised"):
         # row-major C = A B is column-major C^T = B^T A^T
         probs.append((n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), Ni))
     _bind_current_stream(torch)
-    rc, bad = ozaki2_dgemm_batched(probs, _mode(mode))
+    rc, bad, used = ozaki2_dgemm_batched(probs, _mode(mode), 0.0 if target is None else target)
     if rc:
         raise Ozaki2Error(f"ozaki2_dgemm_batched (problem {bad})", rc)
-    return [c for _, _, c in outs]
+    Cs = [c for _, _, c in outs]
+    return (Cs, used) if return_N else Cs

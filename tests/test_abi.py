@@ -117,7 +117,7 @@ def test_k_limits_of_the_header():
     bad = ctypes.c_int(-1)
     prob = oz.Oz2Problem(4, 4, 2**17 + 1, 8, 4, 8, 2**17 + 1, 8, 4, 14, 0)
     arr = (oz.Oz2Problem * 1)(prob)
-    assert oz.lib().ozaki2_dgemm_batched(1, arr, 0, ctypes.byref(bad)) == 1 and bad.value == 0
+    assert oz.lib().ozaki2_dgemm_batched(1, arr, 0, 0.0, ctypes.byref(bad)) == 1 and bad.value == 0
 
 
 @pytest.mark.parametrize("args,code", [

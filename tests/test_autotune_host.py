@@ -1,4 +1,5 @@
 """Host-side logic of the N autotuner (CPU only)."""
+import ctypes
 import json
 import math
 from fractions import Fraction
@@ -60,3 +61,43 @@ def test_library_tile_choice_matches_measurements():
     rate, fixed, tot, worst = autotune.fit_tile_model(table)
     assert rate == {1: 1.0, 2: 0.8, 3: 0.5} and fixed == {1: 4, 2: 0, 3: 0}
     assert worst < 0.01
+
+
+def test_library_pick_equals_python_pick():
+    """ozaki2_autotune_N (host code in the library, over the generated table
+    header) picks what autotune.pick_N picks from the JSON, on and between
+    the grid points, beyond both ends, for targets 1e-6 .. 1e-17."""
+    import itertools
+    from paper_2606_29129_amd import ozaki2 as oz
+    ks = [1, 64, 65, 200, 256, 1000, 2048, 2049, 8192, 10000, 16384, 20000, 2**20]
+    phis = [0.0, 0.3, 0.5, 0.5000000001, 0.7, 1.0, 1.25, 2.0, 2.9, 3.0, 3.5, 4.0, 6.0]
+    targets = [1e-6, 1e-9, 1e-12, 1e-13, 3e-14, 1e-15, 4e-16, 1e-16, 1e-17]
+    for k, phi, tg in itertools.product(ks, phis, targets):
+        assert oz.ozaki2_autotune_N(k, phi, tg) == autotune.pick_N(k, phi, tg), (k, phi, tg)
+
+
+def test_table_header_is_generated_from_the_json():
+    with open(autotune.HEADER) as f:
+        assert f.read() == autotune.header_text()
+
+
+def test_autotune_argument_errors():
+    from paper_2606_29129_amd import ozaki2 as oz
+    lib = oz.lib()
+    N = ctypes.c_int(0)
+    assert lib.ozaki2_autotune_N(-1, 1.0, 1e-15, ctypes.byref(N)) == -1
+    assert lib.ozaki2_autotune_N(10, -1.0, 1e-15, ctypes.byref(N)) == -2
+    assert lib.ozaki2_autotune_N(10, float("nan"), 1e-15, ctypes.byref(N)) == -2
+    assert lib.ozaki2_autotune_N(10, 1.0, 0.0, ctypes.byref(N)) == -3
+    assert lib.ozaki2_autotune_N(10, 1.0, 1e-15, None) == -4
+    phi = ctypes.c_double(0)
+    assert lib.ozaki2_estimate_phi(-1, 1, None, 1, ctypes.byref(phi)) == -1
+    assert lib.ozaki2_estimate_phi(4, 4, None, 4, ctypes.byref(phi)) == -3
+    assert lib.ozaki2_estimate_phi(4, 4, 8, 3, ctypes.byref(phi)) == -4
+    assert lib.ozaki2_estimate_phi(0, 4, None, 1, ctypes.byref(phi)) == 0 and phi.value == 0.0
+    # a batch with N = 0 needs a target; nothing is launched
+    prob = oz.Oz2Problem(4, 4, 4, 8, 4, 8, 4, 8, 4, 0, 0)
+    arr = (oz.Oz2Problem * 1)(prob)
+    bad = ctypes.c_int(0)
+    assert lib.ozaki2_dgemm_batched(1, arr, 0, 0.0, ctypes.byref(bad)) == -4
+    assert lib.ozaki2_dgemm_batched(1, arr, 0, 2.0, ctypes.byref(bad)) == -4

@@ -69,11 +69,12 @@ def test_batched_replay_with_new_data_and_edge_problems():
 
 
 def test_batched_argument_errors():
-    rc, bad = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14), (4, 4, 4, 1, 2, 1, 4, 1, 4, 14)])
+    rc, bad, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14),
+                                          (4, 4, 4, 1, 2, 1, 4, 1, 4, 14)])
     assert rc == -5 and bad == 1
-    rc, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=2)
+    rc, _, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=2)
     assert rc == -3
-    rc, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=3)
+    rc, _, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14)], mode=3)
     assert rc == -3
 
 
@@ -101,3 +102,57 @@ def test_batched_nonfinite_row_sets_status_and_nan_row():
             assert np.array_equal(_bits(C[1:]), _bits(C0[1:]))
         else:
             assert np.array_equal(_bits(C), _bits(C0))
+
+
+def _phi_ref(x):
+    """The estimator the library documents, in numpy: unbiased variance of
+    log|x| over the first 2^20 nonzero finite entries in storage order."""
+    x = np.asarray(x, np.float64).ravel()[: 1 << 20]
+    x = np.abs(x[(x != 0) & np.isfinite(x)])
+    if x.size < 2:
+        return 0.0
+    v = float(np.log(x).var(ddof=1))
+    return float(np.sqrt(max(v - 1.0, 0.0)))
+
+
+@pytest.mark.parametrize("rows,cols,ld,phi", [(300, 200, 300, 0.5), (1000, 1500, 1003, 2.7),
+                                              (4, 5, 9, 1.0), (2048, 1024, 2048, 4.0)])
+def test_estimate_phi_matches_numpy(rows, cols, ld, phi):
+    X = inputs.ozaki_matrix(rows, cols, phi, seed=rows)
+    if rows > 10:
+        X[::7] = 0.0                      # zero rows are skipped
+    buf = np.zeros((cols, ld))            # column-major with leading dimension ld
+    buf[:, :rows] = X.T
+    got = oz.ozaki2_estimate_phi(rows, cols, torch.from_numpy(buf).to(DEV), ld)
+    want = _phi_ref(X.T.ravel())          # storage order: column by column
+    assert abs(got - want) <= 1e-9 * max(1.0, want)
+    if rows * cols > 5000:
+        assert abs(got - phi) < 0.1      # and it estimates the distribution's phi
+
+
+def test_batched_autotune_picks_the_python_N_and_same_bits():
+    """N = 0 in a batch: the library's N_used equals the Python autotuner's
+    pick for the same estimates, and C is bit-identical to the batch with
+    those N given explicitly and to single calls."""
+    from paper_2606_29129_amd import autotune
+    rng = np.random.default_rng(9)
+    pairs, want = [], []
+    for i in range(12):
+        m, n, k = (int(x) for x in np.exp(rng.uniform(np.log(8), np.log(400), 3)).round())
+        phi = float(rng.uniform(0.5, 3.0))
+        A, B = inputs.problem(m, n, k, phi, seed=500 + i)
+        pairs.append((torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)))
+        ph = max(_phi_ref(A), _phi_ref(B))
+        want.append(autotune.pick_N(k, ph, 1e-15))
+    outs, used = oz.dgemm_batched(pairs, 0, target=1e-15, return_N=True)
+    assert used == want
+    explicit = oz.dgemm_batched(pairs, used)
+    torch.cuda.synchronize()
+    for (a, b), N, C, E in zip(pairs, used, outs, explicit):
+        assert np.array_equal(_bits(C.cpu().numpy()), _bits(E.cpu().numpy()))
+        assert np.array_equal(_bits(C.cpu().numpy()), _bits(oz.dgemm(a, b, N=N).cpu().numpy()))
+    # mixed: some N given, some left to the library; degenerate problems report 0
+    e = torch.zeros((0, 5), dtype=torch.float64, device=DEV)
+    f = torch.zeros((5, 3), dtype=torch.float64, device=DEV)
+    _, used2 = oz.dgemm_batched(pairs[:3] + [(e, f)], [7, 0, 0, 0], target=1e-15, return_N=True)
+    assert used2 == [7, want[1], want[2], 0]
