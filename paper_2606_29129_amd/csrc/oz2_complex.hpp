@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k2_split_strided_cplx(
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      *reinterpret_cast<uint2*>(out + (int64_t)(c * N + t) * plane) = stage[sb][c][orow][ochunk];
+      nt_store(out + (int64_t)(c * N + t) * plane, stage[sb][c][orow][ochunk]);
   }
 }
 
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k2_split_contig_cplx(
     pack_cplx<LIMBS, EPL>(Lr, Li, t, tab, w);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      *reinterpret_cast<uint2*>(out + (int64_t)(c * N + t) * plane) = w[c];
+      nt_store(out + (int64_t)(c * N + t) * plane, w[c]);
   }
 }
 

@@ -40,7 +40,8 @@ OZ2_HD double norm_entry(double a) {
 // Vectors stored with stride `ld` between consecutive entries (rows of a
 // column-major matrix): entry h of vector v is X[v + h * ld].  One lane per
 // vector (64 consecutive vectors per wave, so every load is a contiguous 512
-// bytes), one wave per chunk.
+// bytes), one wave per chunk; non-temporal loads (the operand is streamed
+// once and does not fit the caches).
 // RESC: the exact mode's second pass, only for vectors whose exponent is
 // kExpRescale (esel), summing the scaled-down entries.
 template <typename T, bool RESC = false>
@@ -62,7 +63,8 @@ __device__ __forceinline__ void k1_partials_strided_body(
     for (int b = 0; b < kKC; b += 16) {
       double a[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = norm_entry<RESC>((double)p[(int64_t)(b + i) * ld]);
+      for (int i = 0; i < 16; ++i)
+        a[i] = norm_entry<RESC>((double)__builtin_nontemporal_load(p + (int64_t)(b + i) * ld));
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         s = ru_add(s, ru_square(a[i]));
