@@ -149,7 +149,10 @@ __device__ __forceinline__ void k4_crt_body(
   // With 4 slices, two passes over the planes, each for 8 of the lane's 16
   // entries (8 of its 16 bytes per plane): half the accumulator registers
   // (occupancy), no extra reads.  With fewer slices one pass.
-  constexpr int PASSES = S >= 4 ? 2 : 1, R = 16 / PASSES;
+  // The plane bytes are loaded in groups of PF planes, the next group's
+  // loads issued before the current group is accumulated, so a wave waits
+  // for memory once per group instead of once per plane.
+  constexpr int PASSES = S >= 4 ? 2 : 1, R = 16 / PASSES, RW = R / 4, PF = 4;
 #pragma unroll
   for (int h = 0; h < PASSES; ++h) {
     double acc[R][S];
@@ -157,8 +160,7 @@ __device__ __forceinline__ void k4_crt_body(
     for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
-    for (int t = 0; t < N; ++t) {
-      uint32_t ws[R / 4];
+    auto load_plane = [&](int t, uint32_t (&ws)[RW]) {
       if constexpr (R == 16) {
         const uint4 w = *reinterpret_cast<const uint4*>(src + (int64_t)t * plane);
         ws[0] = w.x; ws[1] = w.y; ws[2] = w.z; ws[3] = w.w;
@@ -166,6 +168,8 @@ __device__ __forceinline__ void k4_crt_body(
         const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane + 8 * h);
         ws[0] = w.x; ws[1] = w.y;
       }
+    };
+    auto accumulate = [&](int t, const uint32_t (&ws)[RW]) {
       double wt[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
@@ -175,6 +179,22 @@ __device__ __forceinline__ void k4_crt_body(
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
       }
+    };
+    uint32_t cur[PF][RW] = {}, nxt[PF][RW] = {};
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+      if (i < N) load_plane(i, cur[i]);
+    for (int t0 = 0; t0 < N; t0 += PF) {
+#pragma unroll
+      for (int i = 0; i < PF; ++i)
+        if (t0 + PF + i < N) load_plane(t0 + PF + i, nxt[i]);
+#pragma unroll
+      for (int i = 0; i < PF; ++i)
+        if (t0 + i < N) accumulate(t0 + i, cur[i]);
+#pragma unroll
+      for (int i = 0; i < PF; ++i)
+#pragma unroll
+        for (int q = 0; q < RW; ++q) cur[i][q] = nxt[i][q];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
