@@ -19,6 +19,7 @@
 #include "oz2_batched.hpp"
 #include "oz2_complex.hpp"
 #include "oz2_autotune.hpp"
+#include "oz2_fused.hpp"
 
 #include <algorithm>
 
@@ -112,7 +113,7 @@ int tile_config(int64_t m, int64_t n, int64_t k, int N) {
 // modulus and operand, three uint8 product planes per modulus; the squared
 // norms run over 2k components).
 Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm = kBM,
-                   int64_t bn = kBN, int comps = 1) {
+                   int64_t bn = kBN, int comps = 1, bool fused = false) {
   Layout L;
   L.Mp = round_up(m > 0 ? m : 1, bm);
   L.Np = round_up(n > 0 ? n : 1, bn);
@@ -137,9 +138,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm 
   L.cmaxB = acc ? take(4 * (size_t)L.Np) : 0;
   L.barA = acc ? take((size_t)L.Mp * L.Kp) : 0;
   L.barB = acc ? take((size_t)L.Np * L.Kp) : 0;
-  L.RA = take((size_t)comps * N * L.Mp * L.Kp);
+  // the fused path (n <= 64) keeps A's residues and the products in registers
+  L.RA = take(fused ? 0 : (size_t)comps * N * L.Mp * L.Kp);
   L.RB = take((size_t)comps * N * L.Np * L.Kp);
-  L.U = take((size_t)comps * N * L.Mp * L.Np);
+  L.U = take(fused ? 0 : (size_t)comps * N * L.Mp * L.Np);
   L.total = off;
   return L;
 }
@@ -330,7 +332,13 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   const ModTable* tab = D.d_tables + acc_tab * (kMaxN + 1) + N;
 
   const int cfg = tile_config(m, n, k, N);
-  Layout L = make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg]);
+  // Narrow B: conversion of A, products and CRT in one kernel (automatic
+  // tile choice only; a forced tile keeps the separate kernels).
+  const bool fused = !dbg && g_tile_policy == OZ2_TILE_AUTO && n <= kFuseCols &&
+                     N <= kFuseMaxN && mode != OZ2_MODE_ACCURATE && k <= OZ2_K_BLOCK &&
+                     HT.limbs == 2;
+  Layout L = fused ? make_layout(m, n, k, N, mode, kFuseRows, kFuseCols, 1, true)
+                   : make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg]);
   char* ws = nullptr;
   if ((rc = get_workspace(dev, L.total, &ws))) return rc;
 
@@ -402,6 +410,36 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
     }
   }
   clk.mark(1);
+  if (fused) {
+    // K2 for B only, then the fused kernel (stage 2: conversion of A,
+    // products, CRT and unscaling).
+    const int64_t work = L.Np * (L.Kp / kK2EPT);
+    k2_split_contig<T, 2><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
+        B, ldb, n, k, (const int32_t*)(ws + L.eB), tab, N, (int8_t*)(ws + L.RB), L.Np, L.Kp);
+    clk.mark(2);
+    const unsigned grid = (unsigned)((m + kFuseRows - 1) / kFuseRows);
+    const int32_t* eA = (const int32_t*)(ws + L.eA);
+    const int32_t* eB = (const int32_t*)(ws + L.eB);
+    const int8_t* RB = (const int8_t*)(ws + L.RB);
+    switch (N) {
+#define OZ2_FUSED(NP)                                                                     \
+  case NP:                                                                                \
+    k234_fused<T, TO, NP><<<grid, 256, 0, g_stream>>>(A, lda, m, n, k, eA, eB, RB, L.Np,  \
+                                                       L.Kp, tab, C, ldc);                \
+    break;
+      OZ2_FUSED(2) OZ2_FUSED(3) OZ2_FUSED(4) OZ2_FUSED(5) OZ2_FUSED(6) OZ2_FUSED(7)
+      OZ2_FUSED(8) OZ2_FUSED(9) OZ2_FUSED(10) OZ2_FUSED(11) OZ2_FUSED(12) OZ2_FUSED(13)
+      OZ2_FUSED(14) OZ2_FUSED(15) OZ2_FUSED(16)
+#undef OZ2_FUSED
+      default: return OZ2_ERR_UNSUPPORTED;
+    }
+    clk.mark(3);
+    clk.mark(4);
+    clk.mark(5);
+    if (hipGetLastError() != hipSuccess) return OZ2_ERR_HIP;
+    clk.finish();
+    return 0;
+  }
   // K2: integers and residues.
   switch (HT.limbs) {
     case 2: launch_split<T, 2>(A, lda, B, ldb, m, n, k, L, ws, tab, N); break;

@@ -76,3 +76,35 @@ def test_every_entry_within_componentwise_bound(full_problem):
         bad = int((diff > bound).sum())
         assert bad == 0, f"{bad} entries of rows {r0}..{r0 + 4095} outside the bound"
         del Cn, bound, diff
+
+
+def test_skinny_full_size_fused_equals_unfused_and_oracle():
+    """m = 65536, n = 64, k = 4096 (the skinny configuration), N = 14: the
+    fused kernel's C equals the separate kernels' on all 2^22 entries and the
+    oracle on sampled entries, bit for bit."""
+    dev = torch.device("cuda:0")
+    m, n, k, N = 65536, 64, 4096, 14
+    A = inputs.ozaki_matrix_torch(m, k, 1.0, 0, 0, dev)
+    B = inputs.ozaki_matrix_torch(k, n, 1.0, 0, 1, dev)
+    A_cm, B_cm = A.t().contiguous(), B.t().contiguous()
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    outs = []
+    for tile in (0, 3):
+        C_cm = torch.empty((n, m), dtype=torch.float64, device=dev)
+        assert oz.ozaki2_set_tile(tile) == 0
+        print(f"skinny {m}x{n}x{k} tile policy {tile}", flush=True)
+        assert oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, N, 0) == 0
+        torch.cuda.synchronize()
+        outs.append(C_cm)
+    oz.ozaki2_set_tile(0)
+    assert torch.equal(outs[0].view(torch.int64), outs[1].view(torch.int64))
+    pp = constants.p_prime_prop(N)
+    rng = np.random.default_rng(5)
+    for i, j in [(0, 0), (m - 1, n - 1), (12345, 17)] + [
+            tuple(int(x) for x in (rng.integers(m), rng.integers(n))) for _ in range(5)]:
+        row, col = A[i].cpu().numpy(), B[:, j].cpu().numpy()
+        ei = scaling.alg2_log2_mu(scaling.norm_sq_ru(row), pp)
+        fj = scaling.alg2_log2_mu(scaling.norm_sq_ru(col), pp)
+        c, _, _ = ref.entry(row, col, ei, fj, N)
+        g = float(outs[0][j, i])
+        assert np.float64(g).view(np.uint64) == np.float64(c).view(np.uint64), (i, j)

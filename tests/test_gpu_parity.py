@@ -425,3 +425,69 @@ def test_exact_mode_sgemm_parity():
     torch.cuda.synchronize()
     got = Cd.cpu().numpy().T.copy()
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+# --- fused path for n <= 64 (conversion of A, products and CRT in one kernel) --
+
+def _forced_unfused(A, B, N, mode=0):
+    """The separate K2/K3/K4 path (a forced 256 x 64 tile disables fusion)."""
+    assert oz.ozaki2_set_tile(3) == 0
+    try:
+        return _gpu_dgemm(A, B, N, mode=mode)
+    finally:
+        oz.ozaki2_set_tile(0)
+
+
+@pytest.mark.parametrize("m,n,k,N,mode,phi", [
+    (300, 64, 500, 14, 0, 1.0),
+    (1000, 17, 4097, 14, 0, 0.5),     # k not a multiple of the 64-byte step
+    (65, 1, 33, 2, 0, 2.0),
+    (129, 63, 129, 16, 1, 1.0),
+    (200, 40, 300, 9, 3, 4.0),
+    (16, 64, 64, 12, 0, 1.0),
+    (1, 5, 7, 5, 0, 1.0),
+])
+def test_fused_narrow_b_matches_oracle_and_unfused(m, n, k, N, mode, phi):
+    """n <= 64 and N <= 16 take the fused kernel: C equals the oracle and the
+    separate kernels bit for bit."""
+    print(f"case fused m={m} n={n} k={k} N={N} mode={mode}", flush=True)
+    A, B = inputs.problem(m, n, k, phi, seed=m + 3 * n + k)
+    which = (ref.REVISED, ref.ORIGINAL, None, ref.EXACT)[mode]
+    C = _gpu_dgemm(A, B, N, mode=mode)
+    assert _bits_equal(C, ref.gemm(A, B, N, which)["C"])
+    assert _bits_equal(C, _forced_unfused(A, B, N, mode))
+
+
+def test_fused_nonfinite_rows_and_columns_and_padding():
+    A, B = inputs.problem(90, 30, 200, 1.0, seed=71)
+    A[7, 3] = np.nan
+    B[11, 4] = np.inf
+    C = _gpu_dgemm(A, B, 14, ldc=97)
+    assert np.isnan(C[7]).all() and np.isnan(C[:, 4]).all()
+    assert _bits_equal(C, _forced_unfused(A, B, 14))
+    rows = [i for i in range(90) if i != 7]
+    cols = [j for j in range(30) if j != 4]
+    assert _bits_equal(C[np.ix_(rows, cols)], ref.gemm(A[rows], B[:, cols], 14)["C"])
+
+
+def test_fused_sgemm_matches_unfused():
+    A, B = inputs.problem(150, 48, 260, 1.0, seed=72)
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    m, k = A32.shape
+    n = B32.shape[1]
+
+    def run(tile):
+        Ad, lda = _colmajor(A32)
+        Bd, ldb = _colmajor(B32)
+        Cd = torch.zeros((n, m), dtype=torch.float32, device=DEV)
+        assert oz.ozaki2_set_tile(tile) == 0
+        oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        assert oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, 7, 0) == 0
+        torch.cuda.synchronize()
+        oz.ozaki2_set_tile(0)
+        return Cd.cpu().numpy().T.copy()
+
+    fused = run(0)
+    want = ref.sgemm(A32, B32, 7)
+    assert np.array_equal(fused.view(np.uint32), want.view(np.uint32))
+    assert np.array_equal(fused.view(np.uint32), run(3).view(np.uint32))
