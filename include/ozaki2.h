@@ -224,7 +224,9 @@ int ozaki2_query_constants(int N, int32_t* moduli, float* p_prime_prop,
  * *calls the number of calls timed, then resets the sums.
  * Stages: 0 norms and exponents (K1; in accurate mode also the bar matrices
  * and their INT8 GEMM), 1 convert and split (K2), 2 INT8 GEMMs (K3), 3 CRT
- * and unscale (K4), 4 other (zero fill, bookkeeping).
+ * and unscale (K4), 4 other (zero fill, bookkeeping).  When the fused kernel
+ * for narrow B runs (see ozaki2_set_tile), stage 1 holds K2 for B only and
+ * stage 2 the fused conversion of A, products and CRT.
  */
 #define OZ2_NUM_STAGES 5
 int ozaki2_set_timing(int enable);
@@ -235,7 +237,11 @@ int ozaki2_get_stage_times(double* ms, int* calls);
  * batched path always uses 128 x 128).  OZ2_TILE_AUTO (the default) picks per
  * call from m, n, k and N with a cost model of padded work and workgroup
  * rounds; the others force one shape (rows x columns of C per workgroup).
- * Results do not depend on the tile.  ozaki2_set_tile returns 0, or -1 for
+ * Under OZ2_TILE_AUTO a narrow B (n <= 64) with N <= 16, a fast or exact
+ * mode and k <= OZ2_K_BLOCK runs a fused kernel instead (conversion of A,
+ * the N products on 16 x 16 blocks and the CRT in one pass, nothing
+ * materialised for A); a forced tile always runs the separate kernels.
+ * Results do not depend on the tile or on the fusion.  ozaki2_set_tile returns 0, or -1 for
  * an unknown value; ozaki2_get_tile writes the tile a call with these sizes
  * would use and returns 0, or minus the index of a bad argument.
  */
