@@ -22,6 +22,8 @@
 // accumulator r of lane l is row 4 (l / 16) + r, column l % 16.
 #pragma once
 
+#include <utility>
+
 #include "oz2_k1_norm.hpp"
 #include "oz2_k2_split.hpp"
 #include "oz2_k3_gemm.hpp"
@@ -47,6 +49,40 @@ constexpr int fuse_slices(int NP) {
   int bits = 0;
   while (P) { ++bits; P >>= 1; }
   return (bits + kSliceBits - 1) / kSliceBits;
+}
+
+// 2^40 mod p (the weight of the high limb) and RN(1/p), as the host tables
+// compute them, at compile time: the moduli of the fused kernel are template
+// constants, so their constants need no table loads in the inner loop.
+constexpr double fuse_pow40(int p) {
+  unsigned long long r = 1;
+  for (int i = 0; i < kLimbBits; ++i) r = (r * 2) % (unsigned long long)p;
+  return (double)r;
+}
+
+template <typename F, int... I>
+__device__ __forceinline__ void fuse_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(integral_constant<int, t>) for t = 0 .. NP-1, in order.
+template <int NP, typename F>
+__device__ __forceinline__ void fuse_for(F&& f) {
+  fuse_for_impl(f, std::make_integer_sequence<int, NP>{});
+}
+
+// Residue of a' (two limbs) for modulus index t: as residue_256 / residue_odd
+// with the table values of modulus t.
+template <int t>
+__device__ __forceinline__ int fuse_residue(const Limbs<2>& L) {
+  if constexpr (t == 0) {
+    return residue_256<2>(L);
+  } else {
+    constexpr double p = (double)kModuli[t], ip = 1.0 / (double)kModuli[t];
+    constexpr double c1 = fuse_pow40(kModuli[t]);
+    const double y = fma(L.x[1], c1, L.x[0]);
+    const double q = rint(y * ip);
+    return (int)fma(-q, p, y);
+  }
 }
 
 // NP = N (a template parameter, so that every accumulator access and product
@@ -117,22 +153,36 @@ __global__ __launch_bounds__(256) void k234_fused(
     }
     __syncthreads();       // every wave's part of slab s; every wave done with slab s - 1
     if (more) load_b(buf ^ 1, k0 + kFuseK);
-#pragma unroll
-    for (int t = 0; t < NP; ++t) {
-      uint32_t w[4];
-      pack_residues<2, 16>(L, t, tab, w);
-      const v4i af = {(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    // One plane at a time (fences keep the scheduler from hoisting every
+    // plane's work, which would exhaust the registers): the plane's four
+    // fragment reads first, so that its residue arithmetic covers their
+    // latency, then the products.
+    fuse_for<NP>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      v4i bf[4];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) {
         const int col = cb * 16 + (lane & 15);
-        const v4i bf = *reinterpret_cast<const v4i*>(lds[buf] + t * PB + col * kFuseK +
-                                                     fuse_swz(col, lane >> 4) * 16);
-        acc[t][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf, acc[t][cb], 0, 0, 0);
+        bf[cb] = *reinterpret_cast<const v4i*>(lds[buf] + t * PB + col * kFuseK +
+                                               fuse_swz(col, lane >> 4) * 16);
       }
-      // one plane at a time: keeps the scheduler from hoisting every plane's
-      // fragment reads and residue arithmetic (register pressure)
       __builtin_amdgcn_sched_barrier(0);
-    }
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          b |= ((uint32_t)(uint8_t)(int8_t)fuse_residue<t>(L[4 * q + i])) << (8 * i);
+        w[q] = b;
+      }
+      const v4i af = {(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        acc[t][cb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[cb], acc[t][cb], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    });
   }
 
   // Epilogue: per output, U_t = C_t mod p_t in [0, p_t) (as the GEMM's own
