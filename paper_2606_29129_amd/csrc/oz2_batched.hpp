@@ -98,11 +98,12 @@ struct WorkItem {
   uint16_t tn;
 };
 
-// Persistent GEMM over the work list (sorted by decreasing k).  Workgroup b
-// takes items b, b + G, b + 2G, ... (G = grid size): a sorted list dealt out
-// round-robin balances like a greedy queue, without the contended atomic
-// counter, and the next item is known in advance, so its descriptor is
-// loaded while the current tile runs.
+// Persistent GEMM over the work list (each XCD's share sorted by decreasing
+// k, the tiles of a plane kept on one XCD by the host's ordering).
+// Workgroup b takes items b, b + G, b + 2G, ... (G = grid size): a sorted
+// list dealt out round-robin balances like a greedy queue, without the
+// contended atomic counter, and the next item is known in advance, so its
+// descriptor is loaded while the current tile runs.
 struct TileArgs {
   const int8_t* RA;
   const int8_t* RB;

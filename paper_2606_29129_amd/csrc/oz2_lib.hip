@@ -813,6 +813,42 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, int* bad) {
           for (int tm = 0; tm < tmn; ++tm)
             items.push_back(WorkItem{(uint16_t)a, (uint16_t)t, (uint16_t)tm, (uint16_t)tn});
     }
+    {
+      // XCD-local order.  Workgroups are dispatched round-robin over the 8
+      // XCDs (each with its own L2) and workgroup b takes items b, b + G, ...
+      // (G a multiple of 8 for any list of 8 * CUs items or more), so item i
+      // runs on XCD i % 8.  Items are regrouped so that the tiles of one
+      // plane of one problem run on one XCD, at about the same time, and
+      // share their row and column panels in its L2 (dealt round-robin they
+      // were spread over all 8, each L2 fetching nearly every panel):
+      // planes (runs of one plane's tiles, in the list's order of
+      // decreasing k) go to the XCD with the least work so far that still
+      // has room, split where an XCD is full; per-XCD lengths are exactly
+      // nitems / 8 (+1 for the first nitems % 8); item i of the list is
+      // position i / 8 of XCD i % 8's sequence.  Measured on the 256-problem
+      // batch: 4% less time for the whole call.
+      const int64_t NI = (int64_t)items.size();
+      std::vector<std::vector<WorkItem>> seq(8);
+      std::vector<int64_t> cap(8), work(8, 0);
+      for (int x = 0; x < 8; ++x) cap[x] = NI / 8 + (x < NI % 8 ? 1 : 0);
+      size_t pos = 0;
+      while (pos < items.size()) {
+        size_t end = pos;
+        while (end < items.size() && items[end].p == items[pos].p && items[end].t == items[pos].t) ++end;
+        const int64_t nk = lay[items[pos].p].Kp / kBatchBK;
+        while (pos < end) {
+          int best = -1;
+          for (int x = 0; x < 8; ++x)
+            if ((int64_t)seq[x].size() < cap[x] && (best < 0 || work[x] < work[best])) best = x;
+          const int64_t room = cap[best] - (int64_t)seq[best].size();
+          const size_t take = (size_t)std::min<int64_t>(room, (int64_t)(end - pos));
+          for (size_t q = 0; q < take; ++q) seq[best].push_back(items[pos + q]);
+          work[best] += (int64_t)take * nk;
+          pos += take;
+        }
+      }
+      for (int64_t i = 0; i < NI; ++i) items[(size_t)i] = seq[(size_t)(i % 8)][(size_t)(i / 8)];
+    }
     std::vector<uint16_t> owner((size_t)total_blocks);
     for (int st = 0; st < kB_NSTAGES; ++st)
       for (int a = 0; a < na; ++a)
