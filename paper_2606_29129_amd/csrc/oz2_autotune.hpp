@@ -51,11 +51,16 @@ __global__ __launch_bounds__(256) void k_logstats(const StatSrc* __restrict__ sr
   __shared__ double red[3][256];
   const int op = blockIdx.x / kStatBlocks, sub = blockIdx.x % kStatBlocks;
   const StatSrc s = src[op];
+  // The operand pointer comes from a descriptor, so the compiler cannot tell
+  // it is global memory; read through a global pointer (generic loads would
+  // be flat accesses, each waited for before the next use).
+  typedef __attribute__((address_space(1))) const double GlobalDouble;
+  GlobalDouble* X = (GlobalDouble*)s.X;
   double c = 0.0, sum = 0.0, sq = 0.0;
   for (int64_t g = (int64_t)sub * 256 + threadIdx.x; g < s.count;
        g += (int64_t)kStatBlocks * 256) {
     const int64_t i = g % s.rows, h = g / s.rows;
-    const double x = fabs(s.X[i + h * s.ld]);
+    const double x = fabs(X[i + h * s.ld]);
     if (x > 0.0 && x <= 1.7976931348623157e308) {
       const double l = log(x);
       c += 1.0;

@@ -34,8 +34,46 @@ struct BatchProb {
   int64_t k1a_gx;  // K1 strided grid width (height is ceil(nch/4))
 };
 
-// k slab of the batched GEMM tile (bytes).
-constexpr int kBatchBK = 64;
+// The same descriptor as the device reads it: every pointer in the global
+// address space (the table in the constant one; the kernels never write
+// it).  Read through generic pointers, the element-wise bodies' loads and
+// stores were flat accesses, which complete out of order, so every use of a
+// loaded value waited for all outstanding memory operations; typed loads
+// let the compiler emit global (and scalar) accesses and keep the bodies'
+// own prefetching.
+#define OZ2_GLOBAL __attribute__((address_space(1)))
+struct BatchProbDev {
+  const double OZ2_GLOBAL* A;
+  const double OZ2_GLOBAL* B;
+  double OZ2_GLOBAL* C;
+  int64_t m, n, k, lda, ldb, ldc;
+  int64_t Mp, Np, Kp, nch;
+  int N, mode;
+  __attribute__((address_space(4))) const ModTable* tab;
+  int32_t OZ2_GLOBAL* eA;
+  int32_t OZ2_GLOBAL* eB;
+  double OZ2_GLOBAL* partA;
+  double OZ2_GLOBAL* partB;
+  double OZ2_GLOBAL* maxA;
+  double OZ2_GLOBAL* maxB;
+  double OZ2_GLOBAL* SA;
+  double OZ2_GLOBAL* SB;
+  int8_t OZ2_GLOBAL* RA;
+  int8_t OZ2_GLOBAL* RB;
+  uint8_t OZ2_GLOBAL* U;
+  int64_t k1a_gx;
+};
+#undef OZ2_GLOBAL
+static_assert(sizeof(BatchProbDev) == sizeof(BatchProb) &&
+                  offsetof(BatchProbDev, tab) == offsetof(BatchProb, tab) &&
+                  offsetof(BatchProbDev, U) == offsetof(BatchProb, U) &&
+                  offsetof(BatchProbDev, k1a_gx) == offsetof(BatchProb, k1a_gx),
+              "device view of the descriptor");
+
+// k slab of the batched GEMM tile (bytes): 128 (Kp is a multiple of 128, so
+// no more padding than 64) at two workgroups per CU (64 KiB of LDS each)
+// measured 1-2% faster than 64-byte slabs at three.
+constexpr int kBatchBK = 128;
 
 // The fast modes need at most 2 limbs of 40 bits for |a'| (< 2^79 at N = 20).
 constexpr int kBatchLimbs = 2;
@@ -56,42 +94,53 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
   const int64_t b = blockIdx.x;
   const int p = owner[b];
   const int64_t local = b - pre[p];
-  const BatchProb& P = probs[p];
+  const BatchProbDev& P = reinterpret_cast<const BatchProbDev*>(probs)[p];
+  // Generic pointers for the bodies, each converted from its typed load (the
+  // compiler carries the global address space into the inlined bodies).
+  const double* A = (const double*)P.A;
+  const double* B = (const double*)P.B;
+  const ModTable* tab = (const ModTable*)P.tab;
+  int32_t* eA = (int32_t*)P.eA;
+  int32_t* eB = (int32_t*)P.eB;
   switch (STAGE) {
     case kB_K1A: {
       int64_t bx = local % P.k1a_gx, by = local / P.k1a_gx;
-      k1_partials_strided_body<double>(P.A, P.lda, P.m, P.k, P.nch, P.partA, P.maxA, bx, by);
+      k1_partials_strided_body<double>(A, P.lda, P.m, P.k, P.nch, (double*)P.partA,
+                                       (double*)P.maxA, bx, by);
       break;
     }
     case kB_K1B:
-      k1_partials_contig_body<double>(P.B, P.ldb, P.n, P.k, P.nch, P.partB, P.maxB, local);
+      k1_partials_contig_body<double>(B, P.ldb, P.n, P.k, P.nch, (double*)P.partB,
+                                      (double*)P.maxB, local);
       break;
     case kB_FOLDA:
-      k1_fold_body(P.partA, P.maxA, P.nch, P.m, P.mode, P.tab, P.eA, P.SA, status, local);
+      k1_fold_body((double*)P.partA, (double*)P.maxA, P.nch, P.m, P.mode, tab, eA,
+                   (double*)P.SA, status, local);
       break;
     case kB_FOLDB:
-      k1_fold_body(P.partB, P.maxB, P.nch, P.n, P.mode, P.tab, P.eB, P.SB, status, local);
+      k1_fold_body((double*)P.partB, (double*)P.maxB, P.nch, P.n, P.mode, tab, eB,
+                   (double*)P.SB, status, local);
       break;
     case kB_K2A: {
       const int64_t gx = P.Mp / kK2VB;
       int64_t bx = local % gx, by = local / gx;
-      k2_split_strided_body<double, kBatchLimbs>(P.A, P.lda, P.m, P.k, P.eA, P.tab, P.N, P.RA, P.Mp,
-                                       P.Kp, bx, by);
+      k2_split_strided_body<double, kBatchLimbs>(A, P.lda, P.m, P.k, eA, tab, P.N, (int8_t*)P.RA,
+                                                 P.Mp, P.Kp, bx, by);
       break;
     }
     case kB_K2B:
-      k2_split_contig_body<double, kBatchLimbs>(P.B, P.ldb, P.n, P.k, P.eB, P.tab, P.N, P.RB, P.Np, P.Kp,
-                                      local);
+      k2_split_contig_body<double, kBatchLimbs>(B, P.ldb, P.n, P.k, eB, tab, P.N, (int8_t*)P.RB,
+                                                P.Np, P.Kp, local);
       break;
     default:
-      k4_crt_body<4, double>(P.U, P.eA, P.eB, P.tab, P.N, P.m, P.n, P.Mp, P.Np, P.C, P.ldc,
-                             local);
+      k4_crt_body<4, double>((uint8_t*)P.U, eA, eB, tab, P.N, P.m, P.n, P.Mp, P.Np,
+                             (double*)P.C, P.ldc, local);
       break;
   }
 }
 
 // Work item: problem (16 bits), plane (8 bits), tile row, tile column.
-struct WorkItem {
+struct __attribute__((aligned(8))) WorkItem {
   uint16_t p;
   uint16_t t;
   uint16_t tm;
@@ -104,20 +153,36 @@ struct WorkItem {
 // list dealt out round-robin balances like a greedy queue, without the
 // contended atomic counter, and the next item is known in advance, so its
 // descriptor is loaded while the current tile runs.
+typedef __attribute__((address_space(1))) uint8_t GlobalU8;
+typedef __attribute__((address_space(4))) const ModTable ConstTable;
 struct TileArgs {
   const int8_t* RA;
   const int8_t* RB;
-  uint8_t* U;
+  GlobalU8* U;
   int64_t m, n, Mp, Np, Kp;
-  const ModTable* tab;
+  ConstTable* tab;
   int t, tm, tn;
 };
 
+// The descriptor's pointers are generic; the ones the tile writes through
+// (U) and reads its constants from (tab) are cast to the global and the
+// constant address space (kept so across the loop, where a cast pair
+// would fold away).  Through generic pointers the epilogue's stores
+// were flat stores and its reads of p_t flat loads, and flat accesses
+// complete out of order: every use of p_t then waited for all outstanding
+// memory operations, the previous 16-byte store of the tile included, so
+// each tile paid its store round trips one after another.  The work item is
+// read as one 8-byte word through the constant address space (the list is
+// not written by the kernel and i is the same in every lane), a scalar load.
 __device__ __forceinline__ TileArgs tile_args(const BatchProb* __restrict__ probs,
                                               const WorkItem* __restrict__ items, int i) {
-  const WorkItem w = items[i];
-  const BatchProb& P = probs[w.p];
-  return TileArgs{P.RA, P.RB, P.U, P.m, P.n, P.Mp, P.Np, P.Kp, P.tab, w.t, w.tm, w.tn};
+  typedef __attribute__((address_space(4))) const uint64_t ConstWord;
+  const uint64_t raw = ((ConstWord*)items)[__builtin_amdgcn_readfirstlane(i)];
+  const int p = (int)(raw & 0xFFFF), t = (int)((raw >> 16) & 0xFFFF);
+  const int tm = (int)((raw >> 32) & 0xFFFF), tn = (int)(raw >> 48);
+  const BatchProb& P = probs[p];
+  return TileArgs{P.RA, P.RB, (GlobalU8*)P.U, P.m, P.n, P.Mp, P.Np, P.Kp, (ConstTable*)P.tab,
+                  t, tm, tn};
 }
 
 __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ probs,
@@ -130,12 +195,12 @@ __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ pro
     const int inext = i + (int)gridDim.x;
     const bool more = inext < nitems;
     const TileArgs nxt = tile_args(probs, items, more ? inext : i);
-    // A 128 x 128 tile has only 4 MFMAs per k step per wave; with 64-byte
-    // k slabs (32 KiB of LDS) three workgroups share a CU, hiding the
+    // A 128 x 128 tile has only 4 MFMAs per k step per wave; two
+    // workgroups share a CU (64 KiB of LDS each), hiding part of the
     // per-item latency of the small problems; barrier at the slab top.
-    gemm_tile<kBatchTile, kBatchTile, kBatchBK, 0, false, 2>(cur.RA, cur.RB, cur.U, nullptr, nullptr,
-                                                        cur.m, cur.n, cur.Mp, cur.Np, cur.Kp,
-                                                        cur.tab, cur.t, cur.tm, cur.tn, lds);
+    gemm_tile<kBatchTile, kBatchTile, kBatchBK, 0, false, 2>(
+        cur.RA, cur.RB, (uint8_t*)cur.U, nullptr, nullptr, cur.m, cur.n, cur.Mp, cur.Np, cur.Kp,
+        (const ModTable*)cur.tab, cur.t, cur.tm, cur.tn, lds);
     if (!more) break;
     __syncthreads();  // every wave is done with the LDS before the next prologue
     i = inext;

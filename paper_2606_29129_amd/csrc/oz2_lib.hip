@@ -866,9 +866,9 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, int* bad) {
 
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // three resident workgroups per CU (32 KiB of LDS, <= 168 VGPRs each;
-    // forcing four, at <= 128 registers, measured 6% slower)
-    const int64_t gemm_grid = std::min<int64_t>(nitems, (int64_t)cus * 3);
+    // two resident workgroups per CU (64 KiB of LDS each; 64-byte slabs at
+    // three per CU measured 1-2% slower, four at <= 128 registers 6% slower)
+    const int64_t gemm_grid = std::min<int64_t>(nitems, (int64_t)cus * 2);
 
     // Capture: reset status, refresh descriptors, stages, GEMM, CRT.
     hipStream_t cs = g_batch.cap;
