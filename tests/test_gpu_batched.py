@@ -68,6 +68,36 @@ def test_batched_replay_with_new_data_and_edge_problems():
                           _bits(oz.dgemm(*pairs[0], N=Ns[0]).cpu().numpy()))
 
 
+def test_batched_large_ragged_problems_equal_single_calls():
+    """Problems up to 1500 x 1100 (many tiles per plane, split over XCDs by the
+    work ordering) next to small ones, ragged in every dimension: every
+    result bit-identical to one ozaki2_dgemm call per problem (which picks
+    its own GEMM tile), and sampled entries to the oracle."""
+    shapes = [(1024, 768, 300, 14), (512, 512, 1000, 17), (1500, 1100, 200, 20),
+              (1000, 1020, 129, 8), (700, 600, 64, 12), (100, 2000, 500, 14),
+              (1024, 1024, 1, 6), (37, 45, 1100, 19), (513, 1537, 77, 10)]
+    rng = np.random.default_rng(21)
+    pairs, Ns = [], []
+    for i, (m, n, k, N) in enumerate(shapes):
+        A, B = inputs.problem(m, n, k, float(rng.uniform(0.5, 2.5)), seed=300 + i)
+        pairs.append((torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)))
+        Ns.append(N)
+    print(f"shapes {shapes}", flush=True)
+    for rep in range(2):
+        outs = oz.dgemm_batched(pairs, Ns)
+        torch.cuda.synchronize()
+        for (a, b), N, C in zip(pairs, Ns, outs):
+            assert np.array_equal(_bits(C.cpu().numpy()), _bits(oz.dgemm(a, b, N=N).cpu().numpy()))
+    # a few entries of the largest problem against the oracle, entry by entry
+    A, B = (x.cpu().numpy() for x in pairs[2])
+    C = outs[2].cpu().numpy()
+    for r, c in [(0, 0), (1499, 1099), (777, 3), (5, 1024)]:
+        want = ref.dgemm(A[r:r + 1], B[:, c:c + 1], Ns[2])
+        # one row and one column give the same exponents as in the full
+        # problem (they depend only on that row's and column's norms)
+        assert np.array_equal(_bits(C[r:r + 1, c:c + 1]), _bits(want))
+
+
 def test_batched_argument_errors():
     rc, bad, _ = oz.ozaki2_dgemm_batched([(4, 4, 4, 1, 4, 1, 4, 1, 4, 14),
                                           (4, 4, 4, 1, 2, 1, 4, 1, 4, 14)])
