@@ -1110,7 +1110,7 @@ const char* ozaki2_status_string(int code) {
 
 const char* ozaki2_version(void) {
   return "ozaki2 0.2 gfx950 kc=64 slice=39 limb=40 log2=rn32(log2_f64) "
-         "tiles=256x256x128,128x128x128,256x64x128(auto) batched=128x128x64";
+         "tiles=256x256x128,128x128x128,256x64x128(auto) batched=128x128x128";
 }
 
 int ozaki2_finalize(void) {
