@@ -139,20 +139,19 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
   }
 }
 
-// Work item: problem (16 bits), plane (8 bits), tile row, tile column.
+// Work item: problem, plane, tile row, tile column (16 bits each).
 struct __attribute__((aligned(8))) WorkItem {
   uint16_t p;
   uint16_t t;
   uint16_t tm;
   uint16_t tn;
 };
+// (read on the device as one little-endian 8-byte word: p in bits 0-15, t in
+// 16-31, tm in 32-47, tn in 48-63)
+static_assert(sizeof(WorkItem) == 8 && offsetof(WorkItem, t) == 2 && offsetof(WorkItem, tm) == 4 &&
+                  offsetof(WorkItem, tn) == 6,
+              "work item layout");
 
-// Persistent GEMM over the work list (each XCD's share sorted by decreasing
-// k, the tiles of a plane kept on one XCD by the host's ordering).
-// Workgroup b takes items b, b + G, b + 2G, ... (G = grid size): a sorted
-// list dealt out round-robin balances like a greedy queue, without the
-// contended atomic counter, and the next item is known in advance, so its
-// descriptor is loaded while the current tile runs.
 typedef __attribute__((address_space(1))) uint8_t GlobalU8;
 typedef __attribute__((address_space(4))) const ModTable ConstTable;
 struct TileArgs {
@@ -185,6 +184,12 @@ __device__ __forceinline__ TileArgs tile_args(const BatchProb* __restrict__ prob
                   t, tm, tn};
 }
 
+// Persistent GEMM over the work list (each XCD's share sorted by decreasing
+// k, the tiles of a plane kept on one XCD by the host's ordering).
+// Workgroup b takes items b, b + G, b + 2G, ... (G = grid size): a sorted
+// list dealt out round-robin balances like a greedy queue, without the
+// contended atomic counter, and the next item is known in advance, so its
+// descriptor is loaded while the current tile runs.
 __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ probs,
                                                const WorkItem* __restrict__ items, int nitems) {
   __shared__ __attribute__((aligned(16))) int8_t lds[2][2 * kBatchTile * kBatchBK];
