@@ -816,8 +816,8 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, int* bad) {
     {
       // XCD-local order.  Workgroups are dispatched round-robin over the 8
       // XCDs (each with its own L2) and workgroup b takes items b, b + G, ...
-      // (G a multiple of 8 for any list of 8 * CUs items or more), so item i
-      // runs on XCD i % 8.  Items are regrouped so that the tiles of one
+      // (G = 2 * CUs, a multiple of 8, for any list of that many items or
+      // more), so item i runs on XCD i % 8.  Items are regrouped so that the tiles of one
       // plane of one problem run on one XCD, at about the same time, and
       // share their row and column panels in its L2 (dealt round-robin they
       // were spread over all 8, each L2 fetching nearly every panel):
