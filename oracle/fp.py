@@ -192,7 +192,7 @@ def rn32(x) -> Fraction:
 
 
 # ---------------------------------------------------------------------------
-# Rounded-up sums of squares ("computed with rounding-up", Algorithms 1 and 2)
+# Rounded-up sums of squares (the norm bound of Algorithms 1 and 2)
 # ---------------------------------------------------------------------------
 
 def ru_square(a: float) -> float:

@@ -1,7 +1,8 @@
 """Scale exponents log2(mu_i), log2(nu_j) (test infrastructure only).
 
-* ``norm_sq_ru``       the squared 2-norm "computed with rounding-up"
-                       (Algorithms 1 and 2, Section 4)
+* ``norm_sq_ru``       the squared 2-norm as an upper bound, every square and
+                       addition rounded toward +inf (Algorithms 1 and 2,
+                       Section 4)
 * ``alg2_log2_mu``     Algorithm 2, the proposed scaling (Section 4)
 * ``alg1_log2_mu``     Algorithm 1, the original fast mode (Section 2.3)
 * ``accurate_log2``    accurate mode (Section 2.3)
@@ -28,8 +29,9 @@ Readings taken where the paper leaves a choice open:
   undefined, and every entry of the integer row is 0 whatever the scale.
 * floor(w - t) in Algorithm 2 is taken on the exact difference of the two
   binary32 values.
-* Algorithm 1 evaluates single_up(delta * (log2f(.) + s)) as two rounded
-  binary32 operations: the sum rounded up, then the product rounded up.
+* Algorithm 1 scales the log by delta in binary32 rounded up; this is taken
+  as two binary32 operations, each rounded up: the sum of the mantissa's log
+  and the exponent, then its product with delta.
 * Accurate mode: the paper writes mu_i = mu'^{-1}_i * 2^(...), which does not
   satisfy the bound its own proof derives; the proof needs
   mu_i = mu'_i * 2^(...), which is what is implemented.  The binary32
@@ -77,10 +79,11 @@ def _split_pow2(S: float):
 def alg2_log2_mu(S: float, p_prop: Fraction) -> int:
     """Algorithm 2 (Section 4): log2(mu_i) from the rounded-up squared norm.
 
-        s = floor(log2(a_norm))
-        t = single_up(0.5 * log2f(a_norm / 2**s) + 2 u32)
-        w = single_down(P'_prop - 0.5 s)
-        return floor(w - t)
+    The squared norm S is split into its binary exponent s and a mantissa in
+    [1, 2).  An upper estimate of the mantissa's half-log (half its binary32
+    log2, plus 2 u32 to cover that log's error) is rounded up to binary32;
+    P'_prop - s/2 is rounded down to binary32; the exponent is the floor of
+    their exact difference, so 2 mu_i**2 S stays at most P - 1.
     """
     if not math.isfinite(S):
         raise OverflowError("non-finite squared norm")
@@ -96,9 +99,10 @@ def alg2_log2_mu(S: float, p_prop: Fraction) -> int:
 def alg1_log2_mu(S: float, amax: float, p_fast: Fraction, delta: Fraction) -> int:
     """Algorithm 1 (Section 2.3): log2(mu_i) in the original fast mode.
 
-        s = floor(log2(a_norm))
-        t = single_up(delta * (log2f(a_norm / 2**s) + s))
-        return floor(P'_fast - max(1, t)) - floor(log2(a_max))
+    An upper estimate of half log2 S (the binary32 log2 of S, rounded up,
+    times delta, rounded up again) is clamped from below at 1 and taken from
+    P'_fast; the floor of that, less the exponent of the largest entry
+    magnitude a_max, is the exponent.
     """
     if not math.isfinite(S):
         raise OverflowError("non-finite squared norm")
@@ -171,8 +175,9 @@ def exact_mode_log2_mu(v, P: int):
 
 
 def tilde_log2_ru(x: int) -> Fraction:
-    """tilde-log2 of eq. (flog2), Section 2.3, for an integer x > 0:
-    single_up(log2f(x / 2**floor(log2 x)) + floor(log2 x))."""
+    """tilde-log2 of eq. (flog2), Section 2.3, for an integer x > 0: the
+    binary32 log2 of x's mantissa in [1, 2) plus x's binary exponent, the sum
+    rounded up to binary32."""
     e = fp.floor_log2(Fraction(x))
     L = fp.log2_rn32(fp.ru32(Fraction(x) / fp._pow2(e)))
     return fp.ru32(L + e)

@@ -89,9 +89,13 @@ OZ2_HD int split_pow2(double x, double* frac) {
 OZ2_HD float log2_rn32(float x) { return (float)log2((double)x); }
 
 // Algorithm 2 (Section 4): log2(mu_i) from the rounded-up squared norm S.
-//   s = floor(log2 S); t = RU32(0.5 log2f(S/2^s) + 2u32);
-//   w = RD32(P'_prop - 0.5 s); return floor(w - t).
-// S/2^s is converted to binary32 rounding up; S = 0 gives 0.
+// S is split into its binary exponent and a mantissa in [1, 2); half the
+// binary32 log2 of the mantissa, plus a slack of 2^-23 that covers the log's
+// error, is rounded up (an upper estimate of the fractional half-log); the
+// integer part, P'_prop minus half the exponent, is rounded down.  Their
+// exact difference, floored, is the exponent: never above the largest e with
+// 2^(2e+1) S <= P - 1.  The mantissa goes to binary32 rounding up; S = 0
+// gives 0.
 OZ2_HD int alg2_exponent(double S, float p_prop) {
   if (S == 0.0) return 0;
   double x;
@@ -117,9 +121,10 @@ OZ2_HD int emax_exponent(double S, double pm1_rd) {
   return e;
 }
 
-// Algorithm 1 (Section 2.3): the original fast-mode exponent.
-//   t = RU32(delta * RU32(log2f(S/2^s) + s));
-//   return floor(P'_fast - max(1, t)) - floor(log2 amax).
+// Algorithm 1 (Section 2.3): the original fast-mode exponent.  An upper
+// estimate of half log2 S (the binary32 log2 of S rounded up, times delta,
+// rounded up again; at least 1) is taken from P'_fast, floored, and the
+// exponent of the largest entry magnitude is subtracted.
 OZ2_HD int alg1_exponent(double S, double amax, float p_fast, float delta) {
   if (S == 0.0) return 0;
   double x;
@@ -133,8 +138,8 @@ OZ2_HD int alg1_exponent(double S, double amax, float p_fast, float delta) {
   return e1 - split_pow2(amax, &dummy);
 }
 
-// tilde-log2 of eq. (flog2) for an integer c > 0, rounded up (accurate mode):
-// RU32(log2f(c / 2^floor(log2 c)) + floor(log2 c)).
+// tilde-log2 of eq. (flog2) for an integer c > 0 (accurate mode): the
+// binary32 log2 of c's mantissa plus c's binary exponent, the sum rounded up.
 OZ2_HD float tilde_log2_ru(int64_t c) {
   double x;
   int e = split_pow2((double)c, &x);
@@ -142,8 +147,9 @@ OZ2_HD float tilde_log2_ru(int64_t c) {
   return ru_f32((double)L + (double)e);
 }
 
-// Accurate mode (Section 2.3): log2 mu_i = log2 mu'_i
-//   + floor(P'_accu - RU32(delta * tilde-log2(max_h cbar_ih))).
+// Accurate mode (Section 2.3): the first exponent log2 mu'_i plus the floor
+// of P'_accu less an upper estimate of half log2 of the row's largest bound
+// product (delta times tilde-log2 of it, rounded up).
 OZ2_HD int accurate_exponent(int e_first, int64_t cmax, float p_accu, float delta) {
   if (cmax <= 0) return 0;
   float corr = ru_f32((double)delta * (double)tilde_log2_ru(cmax));

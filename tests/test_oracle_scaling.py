@@ -62,7 +62,7 @@ def _emax(S: float, P: int) -> int:
 
 @pytest.mark.parametrize("N", [2, 8, 14, 16, 20])
 def test_alg2_is_within_one_of_the_exact_maximum(N):
-    """Section 4 defines mu_i as the largest power of two with
+    """Section 4 defines mu_i as the maximal power of two with
     2 mu_i^2 ||a_i||^2 <= P - 1 (up to the 4 u32 slack of the log).  Algorithm 2
     returns that exponent or one less, never more."""
     _, P, _, _ = constants.step1(N)
