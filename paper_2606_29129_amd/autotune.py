@@ -101,17 +101,66 @@ def load_table(path: str = TABLE):
     return _table_cache
 
 
-def pick_N(k: int, phi: float, target: float, table=None, margin: float = 4.0) -> int:
-    """Smallest N whose calibrated max relative error (at the next grid point
-    at or above k and phi) is below target / margin; 20 if none is."""
+def _envelope(t, ks, phis, kg, pg, N):
+    """Largest tabulated error at or below grid point (kg, pg), for N or any
+    larger N."""
+    e = 0.0
+    for k2 in ks:
+        if k2 > kg:
+            break
+        for p2 in phis:
+            if p2 > pg:
+                break
+            row = t["errors"][str(k2)][str(p2)]
+            e = max([e] + [row[str(Nx)] for Nx in (int(x) for x in row.keys()) if Nx >= N])
+    return e
+
+
+def error_estimate(k: int, phi: float, N: int, table=None):
+    """Upper envelope of the calibrated maxima for (k, phi, N): at each grid
+    point the largest tabulated error at or below it, for N or any larger N;
+    between grid points the envelope's log interpolated bilinearly in
+    (log2 k, phi) (end points below the grid); beyond the largest calibrated
+    k scaled by sqrt(k / k_max); None beyond the largest calibrated phi."""
     t = table or load_table()
     ks = sorted(int(x) for x in t["errors"].keys())
-    kk = next((x for x in ks if x >= k), ks[-1])
-    phis = sorted(float(x) for x in t["errors"][str(kk)].keys())
-    pp = next((x for x in phis if x >= phi - 1e-12), phis[-1])
-    row = t["errors"][str(kk)][str(pp)]
-    for N in sorted(int(x) for x in row.keys()):
-        if row[str(N)] * margin <= target:
+    phis = sorted(float(x) for x in t["errors"][str(ks[0])].keys())
+    if phi > phis[-1] + 1e-12:
+        return None
+    kc = max(k, ks[0])
+    i1 = next((i for i, x in enumerate(ks) if x >= kc), len(ks) - 1)
+    i0 = max(i1 - 1, 0)
+    wk = 0.0
+    if i1 > i0:
+        wk = math.log2(kc / ks[i0]) / math.log2(ks[i1] / ks[i0]) if kc < ks[i1] else 1.0
+    pc = max(phi, phis[0])
+    j1 = next((j for j, x in enumerate(phis) if x >= pc - 1e-12), len(phis) - 1)
+    j0 = max(j1 - 1, 0)
+    wp = min((pc - phis[j0]) / (phis[j1] - phis[j0]), 1.0) if j1 > j0 else 0.0
+    if wk in (0.0, 1.0) and wp in (0.0, 1.0):        # on a grid point
+        e = _envelope(t, ks, phis, ks[i0 if wk == 0.0 else i1], phis[j0 if wp == 0.0 else j1], N)
+    else:
+        L = {(a, b): math.log2(_envelope(t, ks, phis, ks[a], phis[b], N))
+             for a in (i0, i1) for b in (j0, j1)}
+        e = 2.0 ** ((1 - wk) * ((1 - wp) * L[i0, j0] + wp * L[i0, j1])
+                    + wk * ((1 - wp) * L[i1, j0] + wp * L[i1, j1]))
+    if k > ks[-1]:
+        e *= math.sqrt(k / ks[-1])
+    return e
+
+
+def pick_N(k: int, phi: float, target: float, table=None, margin: float = 4.0) -> int:
+    """Smallest N whose error estimate (``error_estimate``) is at most
+    target / margin; 20 if none is or phi lies beyond the calibration."""
+    t = table or load_table()
+    ks = sorted(int(x) for x in t["errors"].keys())
+    phis = sorted(float(x) for x in t["errors"][str(ks[0])].keys())
+    Ns = sorted(int(x) for x in t["errors"][str(ks[0])][str(phis[0])].keys())
+    for N in Ns:
+        e = error_estimate(k, phi, N, t)
+        if e is None:
+            break
+        if e * margin <= target:
             return N
     return 20
 
@@ -213,6 +262,7 @@ def measure_tiles(shapes=TILE_SHAPES, Ns=(14, 20), phi=1.0, path: str = TILE_TAB
         Acm, Bcm = A.t().contiguous(), B.t().contiguous()
         C = torch.empty((n, m), dtype=torch.float64, device=dev)
         oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, max(Ns), 0))
         rec = dict(m=m, n=n, k=k, ms={})
         for N in Ns:
             for tile in TILES:

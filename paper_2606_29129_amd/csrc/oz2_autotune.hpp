@@ -6,9 +6,17 @@
 // experiments, (rand - 0.5) exp(phi randn) (Section 3.2), log|a| has variance
 // 1 + phi^2, so phi is estimated from the sample variance of log|a| over the
 // first 2^20 entries of each operand (storage order; zeros and non-finite
-// entries skipped), and N is the smallest number of moduli whose calibrated
-// maximum relative error (oz2_autotune_table.hpp) at the next grid point at or
-// above (k, phi) is at most target / kTuneMargin.
+// entries skipped), and N is the smallest number of moduli whose error
+// estimate is at most target / kTuneMargin.  The estimate is an upper
+// envelope of the calibrated maxima (oz2_autotune_table.hpp), so that the
+// pick never falls when k, phi or the accuracy demand grows even where the
+// single-seed measurements are not monotone: at each grid point the largest
+// tabulated error over every grid point at or below it, for this N or any
+// larger one, and between grid points that envelope's log interpolated
+// bilinearly in (log2 k, phi).  Beyond the largest calibrated k it grows by
+// sqrt(k / k_max) (the scaling keeps about half a bit less per
+// doubling of k: the norm grows with sqrt(k)); beyond the largest calibrated
+// phi there is no basis for an estimate and the pick is the largest N.
 #pragma once
 
 #include <math.h>
@@ -22,17 +30,60 @@ constexpr double kTuneMargin = 4.0;
 constexpr int64_t kPhiSample = int64_t(1) << 20;   // entries per operand
 constexpr int kStatBlocks = 16;                     // blocks per operand
 
-// Smallest N meeting the target at (k, phi) per the calibrated table (the
-// last, largest N when none does).
-inline int tune_pick_N(int64_t k, double phi, double target) {
-  int ik = kTuneNK - 1;
+// Envelope at grid point (ik, ip) for the j-th tabulated N: the largest
+// tabulated error at or below the grid point, for this N or a larger one.
+inline double tune_envelope(int ik, int ip, int j) {
+  double e = 0.0;
+  for (int a = 0; a <= ik; ++a)
+    for (int b = 0; b <= ip; ++b)
+      for (int jj = j; jj < kTuneNN; ++jj) e = e > kTuneErr[a][b][jj] ? e : kTuneErr[a][b][jj];
+  return e;
+}
+
+// Error estimate for (k, phi) with the j-th tabulated N (see above): the
+// envelope's log interpolated bilinearly in (log2 k, phi) between the grid
+// points around (k, phi) (the end points below the grid); a negative value
+// means phi lies beyond the calibrated range.
+inline double tune_error_estimate(int64_t k, double phi, int j) {
+  if (phi > kTunePhi[kTuneNPhi - 1] + 1e-12) return -1.0;
+  const double kc = (double)(k < kTuneK[0] ? kTuneK[0] : k);
+  int k1 = kTuneNK - 1;
   for (int i = 0; i < kTuneNK; ++i)
-    if (kTuneK[i] >= k) { ik = i; break; }
-  int ip = kTuneNPhi - 1;
+    if ((double)kTuneK[i] >= kc) { k1 = i; break; }
+  const int k0 = k1 > 0 ? k1 - 1 : 0;
+  double wk = 0.0;
+  if (k1 > k0)
+    wk = kc < (double)kTuneK[k1]
+             ? log2(kc / (double)kTuneK[k0]) / log2((double)kTuneK[k1] / (double)kTuneK[k0])
+             : 1.0;
+  const double pc = phi < kTunePhi[0] ? kTunePhi[0] : phi;
+  int p1 = kTuneNPhi - 1;
   for (int i = 0; i < kTuneNPhi; ++i)
-    if (kTunePhi[i] >= phi - 1e-12) { ip = i; break; }
-  for (int j = 0; j < kTuneNN; ++j)
-    if (kTuneErr[ik][ip][j] * kTuneMargin <= target) return kTuneN0 + j;
+    if (kTunePhi[i] >= pc - 1e-12) { p1 = i; break; }
+  const int p0 = p1 > 0 ? p1 - 1 : 0;
+  double wp = 0.0;
+  if (p1 > p0) wp = (pc - kTunePhi[p0]) / (kTunePhi[p1] - kTunePhi[p0]);
+  if (wp > 1.0) wp = 1.0;
+  double e;
+  if ((wk == 0.0 || wk == 1.0) && (wp == 0.0 || wp == 1.0)) {
+    e = tune_envelope(wk == 0.0 ? k0 : k1, wp == 0.0 ? p0 : p1, j);   // on a grid point
+  } else {
+    const double l00 = log2(tune_envelope(k0, p0, j)), l01 = log2(tune_envelope(k0, p1, j));
+    const double l10 = log2(tune_envelope(k1, p0, j)), l11 = log2(tune_envelope(k1, p1, j));
+    e = exp2((1.0 - wk) * ((1.0 - wp) * l00 + wp * l01) + wk * ((1.0 - wp) * l10 + wp * l11));
+  }
+  if (k > kTuneK[kTuneNK - 1]) e *= sqrt((double)k / (double)kTuneK[kTuneNK - 1]);
+  return e;
+}
+
+// Smallest N whose error estimate meets the target (the largest N when none
+// does, or when phi lies beyond the calibrated range).
+inline int tune_pick_N(int64_t k, double phi, double target) {
+  for (int j = 0; j < kTuneNN; ++j) {
+    const double e = tune_error_estimate(k, phi, j);
+    if (e < 0.0) break;
+    if (e * kTuneMargin <= target) return kTuneN0 + j;
+  }
   return kTuneN0 + kTuneNN - 1;
 }
 

@@ -101,3 +101,48 @@ def test_autotune_argument_errors():
     bad = ctypes.c_int(0)
     assert lib.ozaki2_dgemm_batched(1, arr, 0, 0.0, ctypes.byref(bad)) == -4
     assert lib.ozaki2_dgemm_batched(1, arr, 0, 2.0, ctypes.byref(bad)) == -4
+
+
+def test_pick_N_on_the_committed_table_is_monotone():
+    """On the committed calibration: the pick never falls when k or phi grow
+    or the target tightens (the envelope), on and between grid points; phi
+    beyond the calibrated range gives N = 20; k beyond it never picks fewer
+    moduli than at the largest calibrated k."""
+    ks = [64, 100, 256, 700, 1024, 2048, 5000, 8192, 16384, 2**16, 2**22]
+    phis = [0.0, 0.5, 0.8, 1.0, 1.5, 2.0, 2.2, 2.5, 3.0, 3.7, 4.0]
+    targets = [1e-9, 1e-12, 1e-14, 1e-15, 3e-16, 1e-16]
+    for t in targets:
+        for phi in phis:
+            picks = [autotune.pick_N(k, phi, t) for k in ks]
+            assert picks == sorted(picks), (phi, t, picks)
+        for k in ks:
+            picks = [autotune.pick_N(k, phi, t) for phi in phis]
+            assert picks == sorted(picks), (k, t, picks)
+    for k in ks:
+        for phi in phis:
+            picks = [autotune.pick_N(k, phi, t) for t in targets]
+            assert picks == sorted(picks), (k, phi, picks)
+    assert autotune.pick_N(1024, 4.5, 1e-6) == 20
+    assert autotune.pick_N(2**22, 0.5, 1e-15) >= autotune.pick_N(16384, 0.5, 1e-15)
+
+
+def test_error_estimate_is_an_envelope_of_the_table():
+    """The estimate at a grid point bounds every tabulated error at or below
+    it (k, phi) for the same or a larger N, and grows by sqrt(k/16384)
+    beyond the calibrated k."""
+    t = autotune.load_table()
+    ks = sorted(int(x) for x in t["errors"])
+    phis = sorted(float(x) for x in t["errors"][str(ks[0])])
+    for k in ks:
+        for phi in phis:
+            for N in autotune.N_GRID:
+                e = autotune.error_estimate(k, phi, N)
+                for k2 in ks:
+                    for p2 in phis:
+                        if k2 <= k and p2 <= phi:
+                            for N2 in autotune.N_GRID:
+                                if N2 >= N:
+                                    assert t["errors"][str(k2)][str(p2)][str(N2)] <= e
+    e16 = autotune.error_estimate(16384, 1.0, 14)
+    assert autotune.error_estimate(4 * 16384, 1.0, 14) == 2 * e16
+    assert autotune.error_estimate(100, 4.01, 14) is None
