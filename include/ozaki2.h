@@ -60,7 +60,9 @@ extern "C" {
 #define OZ2_ERR_K_TOO_LARGE  1 /* k above OZ2_K_MAX (OZ2_K_MAX_ACCURATE in
                                   accurate mode, OZ2_K_BLOCK per problem of a
                                   batch) */
-#define OZ2_ERR_WORKSPACE    2 /* workspace allocation failed */
+#define OZ2_ERR_WORKSPACE    2 /* no workspace large enough was set (see
+                                  ozaki2_set_workspace_policy), or the
+                                  library's own allocation failed */
 #define OZ2_ERR_HIP          3 /* a HIP runtime call failed */
 #define OZ2_ERR_UNSUPPORTED  4 /* valid request this build does not support */
 #define OZ2_ERR_TOO_LARGE    5 /* a size overflows the library's indexing */
@@ -74,11 +76,19 @@ extern "C" {
 /* Limits. */
 #define OZ2_N_MIN 2
 #define OZ2_N_MAX 20
-#define OZ2_K_BLOCK 131072        /* 2^17: k per INT8 GEMM launch; the INT32
+#define OZ2_K_BLOCK 131072        /* 2^17: k per INT8 GEMM launch.  For the
+                                     odd moduli the residues lie in
+                                     [-(p-1)/2, (p-1)/2] and the INT32
                                      products of one block are exact
-                                     (|C_t| <= 2^17 * 127^2 < 2^31; Section 2.2
-                                     requires exact products), larger k is
-                                     summed over blocks modulo p_t */
+                                     (|C_t| <= 2^17 * 127^2 < 2^31).  For p =
+                                     256 the residues lie in [-128, 127] and
+                                     C_0 can reach 2^17 * 128^2 = 2^31, which
+                                     wraps in INT32; C_0 is only used modulo
+                                     256 and 2^32 is a multiple of 256, so
+                                     the result is unaffected (the debug
+                                     product of plane 0 is exact modulo
+                                     2^32).  Larger k is summed over blocks
+                                     modulo p_t */
 #define OZ2_K_MAX 4194304         /* 2^22 (grid limits of the norm and
                                      split kernels) */
 #define OZ2_K_MAX_ACCURATE 262144 /* 2^18: accurate mode's bar product (entries
@@ -101,9 +111,11 @@ extern "C" {
  * the single correctly rounded (nearest-even) value of C''_ij * 2^-(e_i+f_j),
  * where C'' = A'B' is exact (Section 2.2, Step 4).
  *
- * Workspace: device memory set by ozaki2_set_workspace is used if it is
- * large enough (ozaki2_workspace_size); otherwise the library allocates its
- * own (hipMalloc, kept and grown on demand, freed by ozaki2_finalize).
+ * Workspace: the device memory set by ozaki2_set_workspace, which must be at
+ * least ozaki2_workspace_size bytes; otherwise the call returns
+ * OZ2_ERR_WORKSPACE and launches nothing (the library never allocates device
+ * memory on this path unless the caller opts in with
+ * ozaki2_set_workspace_policy(OZ2_WORKSPACE_LIBRARY)).
  */
 int ozaki2_dgemm(int64_t m, int64_t n, int64_t k,
                  const double* A, int64_t lda,
@@ -181,12 +193,22 @@ int ozaki2_set_stream(void* stream);
 int ozaki2_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode,
                           size_t* bytes);
 
-/* Use caller-owned device memory (256-byte aligned) as workspace.  The
- * library does not free it.  Pass (NULL, 0) to go back to library-owned
- * workspace.  The memory must stay valid until replaced and must not be in
- * use by another call in flight on another stream.  Returns 0, or -1 if ptr
- * is not 256-byte aligned. */
+/* Use caller-owned device memory (256-byte aligned) as workspace for every
+ * later call.  The library does not free it.  Pass (NULL, 0) to unset it.
+ * The memory must stay valid until replaced and must not be in use by
+ * another call in flight on another stream.  Returns 0, or -1 if ptr is not
+ * 256-byte aligned. */
 int ozaki2_set_workspace(void* ptr, size_t bytes);
+
+/* What a call does when the caller's workspace is missing or too small.
+ * OZ2_WORKSPACE_CALLER (the default): return OZ2_ERR_WORKSPACE, launch
+ * nothing -- no entry point allocates device memory.  OZ2_WORKSPACE_LIBRARY
+ * (opt-in convenience): the library allocates its own workspace with
+ * hipMalloc (synchronising the device when it grows; kept until
+ * ozaki2_finalize).  Returns 0, or -1 for an unknown policy. */
+#define OZ2_WORKSPACE_CALLER  0
+#define OZ2_WORKSPACE_LIBRARY 1
+int ozaki2_set_workspace_policy(int policy);
 
 /* Synchronise the current stream, then report (in *status) and clear the
  * device status bits (OZ2_STATUS_*) written by the most recent GEMM call on
@@ -286,10 +308,18 @@ typedef struct oz2_problem {
  * ozaki2_dgemm run once for the whole batch (one grid per stage) and the
  * INT8 GEMMs of every problem and modulus run in one persistent kernel over
  * a shared work list.  k <= OZ2_K_BLOCK per problem.  The graph is built on
- * the first call with a given batch signature (shapes, N, mode, workspace)
- * and replayed afterwards; only the matrix pointers are refreshed per call
- * (a small host -> device copy inside the graph).  Results are bit-identical
- * to calling ozaki2_dgemm on each problem with its N_used.
+ * the first call with a given batch signature (shapes, N, mode, device,
+ * workspace address; this call writes the batch's tables into the workspace
+ * and synchronises) and replayed afterwards; a replay whose problems moved
+ * to other matrices first rewrites those pointers with a small kernel
+ * launch (the pointers travel as its arguments).  Every device buffer of
+ * the batch -- status, descriptors, work list, the phi estimate's scratch,
+ * the per-problem regions -- lies in the caller's workspace, which must hold
+ * ozaki2_dgemm_batched_workspace_size bytes (else OZ2_ERR_WORKSPACE, under
+ * the default policy).  With ozaki2_set_timing(1) the same kernels are
+ * launched directly instead of the graph, with stage events as for
+ * ozaki2_dgemm.  Results are bit-identical to calling ozaki2_dgemm on each
+ * problem with its N_used.
  *
  * Returns 0; -1 if batch < 0; -2 if problems is NULL with batch > 0; -3 for
  * an unsupported mode; -4 if some N is 0 and the target is not in (0, 1];
@@ -300,6 +330,15 @@ typedef struct oz2_problem {
 int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode,
                          double target_max_rel_err, int* bad_index);
 
+/* Bytes of workspace an ozaki2_dgemm_batched call with these problems and
+ * mode needs (written to *bytes; 0 if nothing would be computed).  Problems
+ * with N = 0 are counted with OZ2_N_MAX moduli, so the bound holds for any
+ * N the autotuner picks.  Returns 0, -1 batch < 0, -2 problems NULL with
+ * batch > 0, -3 unsupported mode, -4 bytes NULL, or the code
+ * ozaki2_dgemm_batched would return for the first invalid problem. */
+int ozaki2_dgemm_batched_workspace_size(int batch, const oz2_problem* problems, int mode,
+                                        size_t* bytes);
+
 /*
  * The autotuner.  The error of the emulated product is set by the number of
  * moduli (wider integers) and the spread of the entry magnitudes; for the
@@ -309,17 +348,23 @@ int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode,
  * against exact products, per (k, phi, N) grid point (k 64..16384, phi
  * 0.5..4, N 10..20).
  *
- * ozaki2_autotune_N -- host only: *N = the smallest N whose tabulated error
- * at the next grid point at or above (k, phi) is at most target / 4 (20 if
- * none is).  Returns 0; -1 k < 0; -2 phi not >= 0; -3 target not in (0, 1];
- * -4 N is NULL.
+ * ozaki2_autotune_N -- host only: *N = the smallest N whose error estimate
+ * is at most target / 4, 20 if none is.  The estimate is an upper envelope of
+ * the table: the largest tabulated error over every grid point at or below
+ * the grid point that brackets (k, phi) from above, for this N or any larger
+ * one (so the pick never falls as k, phi or the accuracy demand grow); for k
+ * beyond 16384 it is scaled by sqrt(k / 16384); for phi beyond 4 (outside the
+ * calibration) *N = 20.  Returns 0; -1 k < 0; -2 phi not >= 0; -3 target not
+ * in (0, 1]; -4 N is NULL.
  *
  * ozaki2_estimate_phi -- phi of a column-major rows x cols binary64 device
  * matrix (leading dimension ld): sqrt(max(var - 1, 0)) with var the unbiased
  * sample variance of log|x| over its first min(rows cols, 2^20) entries in
  * storage order, zeros and non-finite entries skipped (0 with fewer than two
- * such entries).  Synchronises the stream.  Returns 0; -1..-5 for the
- * argument in that position; or OZ2_ERR_HIP.
+ * such entries).  Uses the first KiB of the workspace (same
+ * workspace rules as ozaki2_dgemm) and synchronises the stream.  Returns 0;
+ * -1..-5 for the argument in that position; OZ2_ERR_WORKSPACE; or
+ * OZ2_ERR_HIP.
  */
 int ozaki2_autotune_N(int64_t k, double phi, double target_max_rel_err, int* N);
 int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld,
@@ -335,7 +380,9 @@ int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld,
  *   RB[N*n*k]         int8 residues of B': element (t, j, h) at t*n*k + j*k + h
  *   Ct[m*n]           int32 product rmod(A',p_t) rmod(B',p_t) for modulus
  *                     index t (0-based), column-major (i + j*m); only for
- *                     k <= OZ2_K_BLOCK (else OZ2_ERR_UNSUPPORTED)
+ *                     k <= OZ2_K_BLOCK (else OZ2_ERR_UNSUPPORTED); for t = 0
+ *                     (p = 256) it is the product modulo 2^32 (see
+ *                     OZ2_K_BLOCK)
  * Test hook for stage-by-stage comparison with a reference.  Synchronises
  * the stream before returning.
  */

@@ -219,12 +219,45 @@ def accurate_log2(A, B, p_accu: Fraction, delta: Fraction):
     assert Abar.size == 0 or Abar.max() <= 127
     Cbar = Abar @ Bbar
 
-    def final(e1, cmax):
-        if e1 is None or cmax == 0:
-            return 0
-        corr = fp.ru32(Fraction(delta) * tilde_log2_ru(int(cmax)))
-        return e1 + math.floor(Fraction(p_accu) - corr)
-
-    emu = [final(ea[i], int(Cbar[i, :].max()) if n else 0) for i in range(m)]
-    enu = [final(eb[j], int(Cbar[:, j].max()) if m else 0) for j in range(n)]
+    emu = [accurate_final_exponent(ea[i], int(Cbar[i, :].max()) if n else 0, p_accu, delta)
+           for i in range(m)]
+    enu = [accurate_final_exponent(eb[j], int(Cbar[:, j].max()) if m else 0, p_accu, delta)
+           for j in range(n)]
     return emu, enu, Abar, Bbar, Cbar
+
+
+def accurate_final_exponent(e1, cmax: int, p_accu: Fraction, delta: Fraction) -> int:
+    """Accurate mode's exponent of one row (column) from its first exponent
+    e1 = log2 mu'_i (None for a zero vector) and the largest entry cmax of
+    its row (column) of Cbar: e1 + floor(P'_accu - delta * tilde-log2(cmax)),
+    the product rounded up to binary32.  0 for a zero vector or cmax = 0."""
+    if e1 is None or cmax == 0:
+        return 0
+    corr = fp.ru32(Fraction(delta) * tilde_log2_ru(int(cmax)))
+    return e1 + math.floor(Fraction(p_accu) - corr)
+
+
+def accurate_bars(X):
+    """Accurate mode's first step for every row of the binary64 matrix X
+    (finite entries), in array form for large checks: returns (e1, nonzero,
+    bar) with e1[i] = 5 - floor(log2 max_h |x_ih|) (0 where the row is zero,
+    flagged False in ``nonzero``) and bar[i, h] = ceil(2**e1[i] |x_ih|) as
+    int64 (<= 64).
+
+    Same values as ``accurate_log2``'s first scale and bar matrices: the
+    exponent of max|x| comes from frexp (exact); 2**e1 |x| is exact in
+    binary64 except where it falls below the normal range, and there its
+    exact value lies in (0, 1), whose ceiling is 1 -- so a positive entry
+    that scales to a (rounded) subnormal or to zero gets 1."""
+    X = np.abs(np.asarray(X, dtype=np.float64))
+    if X.ndim != 2:
+        raise ValueError("X must be a matrix")
+    rows = X.shape[0]
+    amax = X.max(axis=1) if X.shape[1] else np.zeros(rows)
+    nonzero = amax > 0
+    _, ex = np.frexp(np.where(nonzero, amax, 1.0))    # amax = f 2**ex, f in [0.5, 1)
+    e1 = np.where(nonzero, 5 - (ex.astype(np.int64) - 1), 0)
+    bar = np.ceil(np.ldexp(X, e1[:, None].astype(np.int32)))
+    bar = np.where((X > 0) & (bar < 1), 1.0, bar)
+    bar[~nonzero] = 0.0
+    return e1, nonzero, bar.astype(np.int64)

@@ -213,6 +213,28 @@ __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ pro
   }
 }
 
+// Caller pointers of up to kBatchPtrChunk consecutive descriptors, passed as
+// kernel arguments (1.5 KiB): a replay whose problems moved to new matrices
+// rewrites only these fields, stream ordered, with no host buffer that has to
+// outlive the call.
+constexpr int kBatchPtrChunk = 64;
+struct BatchPtrs {
+  const double* A[kBatchPtrChunk];
+  const double* B[kBatchPtrChunk];
+  double* C[kBatchPtrChunk];
+  int first, count;
+};
+
+__global__ void kb_set_ptrs(BatchProb* __restrict__ probs, BatchPtrs p) {
+  const int c = threadIdx.x;
+  if (c < p.count) {
+    BatchProb& q = probs[p.first + c];
+    q.A = p.A[c];
+    q.B = p.B[c];
+    q.C = p.C[c];
+  }
+}
+
 // Status word reset at the start of each replay (a kernel, not a memset, so
 // that it can live in the captured graph).
 __global__ void kb_reset(int* __restrict__ status) {

@@ -44,6 +44,7 @@ _SIGS = {
     "ozaki2_set_stream": ([_vp], _c_int),
     "ozaki2_workspace_size": ([_c_i64] * 3 + [_c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)], _c_int),
     "ozaki2_set_workspace": ([_vp, ctypes.c_size_t], _c_int),
+    "ozaki2_set_workspace_policy": ([_c_int], _c_int),
     "ozaki2_get_device_status": ([ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_status_string": ([_c_int], ctypes.c_char_p),
     "ozaki2_version": ([], ctypes.c_char_p),
@@ -60,6 +61,8 @@ _SIGS = {
     "ozaki2_debug_log2f": ([_vp, _vp, _c_i64], _c_int),
     "ozaki2_dgemm_batched": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int, ctypes.c_double,
                               ctypes.POINTER(_c_int)], _c_int),
+    "ozaki2_dgemm_batched_workspace_size": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int,
+                                             ctypes.POINTER(ctypes.c_size_t)], _c_int),
     "ozaki2_autotune_N": ([_c_i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_c_int)], _c_int),
     "ozaki2_estimate_phi": ([_c_i64, _c_i64, _vp, _c_i64, ctypes.POINTER(ctypes.c_double)], _c_int),
 }
@@ -144,6 +147,13 @@ def ozaki2_set_workspace(ptr, nbytes):
     return lib().ozaki2_set_workspace(_ptr(ptr), nbytes)
 
 
+WORKSPACE_CALLER, WORKSPACE_LIBRARY = 0, 1
+
+
+def ozaki2_set_workspace_policy(policy):
+    return lib().ozaki2_set_workspace_policy(policy)
+
+
 def ozaki2_get_device_status():
     s = ctypes.c_int(0)
     _check("ozaki2_get_device_status", lib().ozaki2_get_device_status(ctypes.byref(s)))
@@ -205,10 +215,7 @@ def ozaki2_debug_stages(m, n, k, A, lda, B, ldb, N, mode, t,
                                      _ptr(RB), _ptr(Ct))
 
 
-def ozaki2_dgemm_batched(problems, mode=MODE_REVISED, target=0.0):
-    """problems: a sequence of Oz2Problem (or of tuples with its fields up to
-    N, pointers as tensors or ints; N = 0 lets the library pick N for the
-    target).  Returns (rc, bad_index, [N_used per problem])."""
+def _problem_array(problems):
     arr = (Oz2Problem * max(1, len(problems)))()
     for i, q in enumerate(problems):
         if isinstance(q, Oz2Problem):
@@ -216,6 +223,23 @@ def ozaki2_dgemm_batched(problems, mode=MODE_REVISED, target=0.0):
         else:
             m, n, k, A, lda, B, ldb, C, ldc, N = q
             arr[i] = Oz2Problem(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, 0)
+    return arr
+
+
+def ozaki2_dgemm_batched_workspace_size(problems, mode=MODE_REVISED):
+    """Workspace bytes of a batch (problems as for ozaki2_dgemm_batched)."""
+    arr = _problem_array(problems)
+    b = ctypes.c_size_t(0)
+    _check("ozaki2_dgemm_batched_workspace_size",
+           lib().ozaki2_dgemm_batched_workspace_size(len(problems), arr, mode, ctypes.byref(b)))
+    return b.value
+
+
+def ozaki2_dgemm_batched(problems, mode=MODE_REVISED, target=0.0):
+    """problems: a sequence of Oz2Problem (or of tuples with its fields up to
+    N, pointers as tensors or ints; N = 0 lets the library pick N for the
+    target).  Returns (rc, bad_index, [N_used per problem])."""
+    arr = _problem_array(problems)
     bad = ctypes.c_int(-1)
     rc = lib().ozaki2_dgemm_batched(len(problems), arr, mode, float(target), ctypes.byref(bad))
     return rc, bad.value, [arr[i].N_used for i in range(len(problems))]
@@ -240,6 +264,34 @@ def ozaki2_debug_log2f(x, y, n):
 
 
 # --- torch conveniences ------------------------------------------------------
+
+_workspaces = {}   # device index -> (uint8 tensor, 256-aligned address, usable bytes)
+
+
+def ensure_workspace(nbytes, device=None):
+    """Point the library at a workspace of at least ``nbytes`` on ``device``
+    (default: the current one): a uint8 torch tensor cached per device and
+    replaced by a larger one when a call needs more.  The library itself
+    never allocates device memory (its default workspace policy); this is
+    where the conveniences below get theirs.  Returns the address."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    cur = _workspaces.get(idx)
+    if cur is None or cur[2] < nbytes:
+        t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=dev)
+        cur = (t, (t.data_ptr() + 255) // 256 * 256, max(int(nbytes), 1))
+        _workspaces[idx] = cur
+    # the tensor is used on the current stream from here on
+    cur[0].record_stream(torch.cuda.current_stream(dev))
+    _check("ozaki2_set_workspace", ozaki2_set_workspace(cur[1], cur[2]))
+    return cur[1]
+
+
+def release_workspaces():
+    """Unset the library's workspace and drop the cached tensors."""
+    ozaki2_set_workspace(None, 0)
+    _workspaces.clear()
 
 def _mode(mode):
     return _MODES[mode] if isinstance(mode, str) else int(mode)
@@ -295,6 +347,9 @@ def _gemm(A, B, N, mode, out, fn):
     if not C.is_contiguous() or C.shape != (m, n):
         raise ValueError("out must be a contiguous m x n tensor")
     _bind_current_stream(torch)
+    size_fn = ozaki2_zgemm_workspace_size if fn in (ozaki2_zgemm, ozaki2_cgemm) else \
+        ozaki2_workspace_size
+    ensure_workspace(size_fn(n, m, k, N, _mode(mode)), A.device)
     # Column-major view: C^T (n x m, ld n) = B^T (n x k, ld n) * A^T (k x m, ld k).
     rc = fn(n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), N, _mode(mode))
     _check(fn.__name__, rc)
@@ -319,6 +374,9 @@ def dgemm_batched(pairs, N=0, mode="revised", target=None, return_N=False):
         # row-major C = A B is column-major C^T = B^T A^T
         probs.append((n, m, k, B, max(1, n), A, max(1, k), C, max(1, n), Ni))
     _bind_current_stream(torch)
+    if outs:
+        ensure_workspace(ozaki2_dgemm_batched_workspace_size(probs, _mode(mode)),
+                         outs[0][0].device)
     rc, bad, used = ozaki2_dgemm_batched(probs, _mode(mode), 0.0 if target is None else target)
     if rc:
         raise Ozaki2Error(f"ozaki2_dgemm_batched (problem {bad})", rc)

@@ -151,3 +151,46 @@ def test_complex_workspace_holds_three_components():
     assert oz.ozaki2_zgemm_workspace_size(0, 5, 5, 14) == 0
     with pytest.raises(oz.Ozaki2Error):
         oz.ozaki2_zgemm_workspace_size(8, 8, 8, 14, 2)
+
+
+def _probs(shapes_N):
+    out = []
+    for m, n, k, N in shapes_N:
+        out.append((m, n, k, 256, max(1, m), 256, max(1, k), 256, max(1, m), N))
+    return out
+
+
+def test_batched_workspace_size_is_a_bound_over_N():
+    """Host only: the batch's workspace size grows with N, counts N = 0 as
+    the maximum N (20) plus scratch for the phi estimate, is at least the sum of the single-call workspaces of
+    its problems (each problem keeps its own regions), and reports argument
+    errors like the batched call."""
+    shapes = [(100, 70, 300), (64, 64, 64), (1500, 33, 900)]
+    sz = {N: oz.ozaki2_dgemm_batched_workspace_size(_probs([s + (N,) for s in shapes]))
+          for N in (8, 14, 20, 0)}
+    # N = 0 plans N = 20 plus the phi estimate's scratch (two operands each)
+    assert sz[8] < sz[14] < sz[20] < sz[0] <= sz[20] + 4096
+    singles = sum(oz.ozaki2_workspace_size(m, n, k, 20, 0) for m, n, k in shapes)
+    assert sz[20] > 0
+    # single-call layouts use 256-row tiles, the batch 128: compare per problem
+    # against its own 128-tile need instead of the single-call figure
+    assert sz[20] >= sum(20 * ((m + 127) // 128 * 128) * ((k + 127) // 128 * 128)
+                         for m, n, k in shapes)
+    assert singles > 0
+    # problems with nothing to compute need no workspace
+    assert oz.ozaki2_dgemm_batched_workspace_size(_probs([(0, 5, 5, 14), (5, 5, 0, 14)])) == 0
+    lib = oz.lib()
+    b = ctypes.c_size_t(0)
+    arr = oz._problem_array(_probs([(4, 4, 4, 14)]))
+    assert lib.ozaki2_dgemm_batched_workspace_size(-1, arr, 0, ctypes.byref(b)) == -1
+    assert lib.ozaki2_dgemm_batched_workspace_size(1, None, 0, ctypes.byref(b)) == -2
+    assert lib.ozaki2_dgemm_batched_workspace_size(1, arr, 2, ctypes.byref(b)) == -3
+    assert lib.ozaki2_dgemm_batched_workspace_size(1, arr, 0, None) == -4
+    bad = oz._problem_array(_probs([(4, 4, 4, 21)]))
+    assert lib.ozaki2_dgemm_batched_workspace_size(1, bad, 0, ctypes.byref(b)) == -10
+
+
+def test_workspace_policy_values():
+    assert oz.ozaki2_set_workspace_policy(2) == -1
+    assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_LIBRARY) == 0
+    assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_CALLER) == 0

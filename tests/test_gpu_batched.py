@@ -153,6 +153,7 @@ def test_estimate_phi_matches_numpy(rows, cols, ld, phi):
         X[::7] = 0.0                      # zero rows are skipped
     buf = np.zeros((cols, ld))            # column-major with leading dimension ld
     buf[:, :rows] = X.T
+    oz.ensure_workspace(1024)              # the estimate's scratch
     got = oz.ozaki2_estimate_phi(rows, cols, torch.from_numpy(buf).to(DEV), ld)
     want = _phi_ref(X.T.ravel())          # storage order: column by column
     assert abs(got - want) <= 1e-9 * max(1.0, want)

@@ -178,6 +178,7 @@ def full_complex():
     C_cm = torch.empty((SIZE, SIZE), dtype=torch.complex128, device=dev)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
     print(f"ozaki2_zgemm {SIZE}^3 N={N_FULL}", flush=True)
+    oz.ensure_workspace(oz.ozaki2_zgemm_workspace_size(SIZE, SIZE, SIZE, N_FULL, 0))
     rc = oz.ozaki2_zgemm(SIZE, SIZE, SIZE, A_cm, SIZE, B_cm, SIZE, C_cm, SIZE, N_FULL, 0)
     assert rc == 0, oz.ozaki2_status_string(rc)
     torch.cuda.synchronize()

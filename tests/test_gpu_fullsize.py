@@ -93,6 +93,7 @@ def test_skinny_full_size_fused_equals_unfused_and_oracle():
         C_cm = torch.empty((n, m), dtype=torch.float64, device=dev)
         assert oz.ozaki2_set_tile(tile) == 0
         print(f"skinny {m}x{n}x{k} tile policy {tile}", flush=True)
+        oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, 0))
         assert oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, N, 0) == 0
         torch.cuda.synchronize()
         outs.append(C_cm)

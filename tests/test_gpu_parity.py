@@ -36,6 +36,7 @@ def _gpu_dgemm(A, B, N, mode=0, lda=None, ldb=None, ldc=None):
     ldc = ldc or max(1, m)
     Cd = torch.full((n, ldc), 7.0, dtype=torch.float64, device=DEV)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, mode))
     rc = oz.ozaki2_dgemm(m, n, k, Ad, lda, Bd, ldb, Cd, ldc, N, mode)
     assert rc == 0, oz.ozaki2_status_string(rc)
     torch.cuda.synchronize()
@@ -62,6 +63,7 @@ def _gpu_stages(A, B, N, mode, t):
     RA, RB = z(N * m * k, torch.int8), z(N * n * k, torch.int8)
     Ct = z(m * n, torch.int32)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, mode))
     rc = oz.ozaki2_debug_stages(m, n, k, Ad, lda, Bd, ldb, N, mode, t,
                                 eA, eB, SA, SB, RA, RB, Ct)
     assert rc == 0, oz.ozaki2_status_string(rc)
@@ -122,7 +124,9 @@ def test_stage_parity_and_result(m, n, k, phi, N, seed):
         for tt in range(N):
             assert np.array_equal(g["RA"][tt], r["RA"][tt]), f"RA plane {tt}"
             assert np.array_equal(g["RB"][tt], r["RB"][tt].T), f"RB plane {tt}"
-        assert np.array_equal(g["Ct"].astype(np.int64), r["G"][t]), f"INT32 product t={t}"
+        # plane 0 (p = 256) is exact modulo 2^32 only (it may reach 2^31)
+        want = r["G"][t] if t else (r["G"][t] + 2**31) % 2**32 - 2**31
+        assert np.array_equal(g["Ct"].astype(np.int64), want), f"INT32 product t={t}"
     C = _gpu_dgemm(A, B, N)
     assert _bits_equal(C, r["C"])
     # determinism: a second run gives the same bits
@@ -253,6 +257,7 @@ def _gpu_sgemm(A, B, N, mode=0):
     Bd, ldb = _colmajor(B.astype(np.float32))
     Cd = torch.empty((n, m), dtype=torch.float32, device=DEV)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, mode))
     rc = oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, N, mode)
     assert rc == 0, oz.ozaki2_status_string(rc)
     torch.cuda.synchronize()
@@ -308,23 +313,47 @@ def test_every_tile_shape_gives_the_same_bits(tile, mode):
         oz.ozaki2_set_tile(0)
 
 
-def test_too_small_caller_workspace_falls_back_to_library_memory():
-    """ozaki2_set_workspace with fewer bytes than a call needs: the call uses
-    library-owned memory instead and the result is unchanged; a large enough
-    caller workspace is used as is."""
-    A, B = inputs.problem(130, 90, 150, 1.0, seed=11)
+def test_workspace_rules():
+    """A missing or too small caller workspace: the call returns
+    OZ2_ERR_WORKSPACE (2) and writes nothing -- the library allocates no
+    device memory by default; with the opt-in policy OZ2_WORKSPACE_LIBRARY it
+    allocates its own and the result is unchanged; a large enough caller
+    workspace is used as is; a misaligned one is refused."""
+    m, n, k = 130, 90, 150
+    A, B = inputs.problem(m, n, k, 1.0, seed=11)
     want = ref.dgemm(A, B, 14)
-    need = oz.ozaki2_workspace_size(130, 90, 150, 14, 0)
+    need = oz.ozaki2_workspace_size(m, n, k, 14, 0)
     small = torch.empty(need // 4, dtype=torch.uint8, device=DEV)
     big = torch.empty(need + 256, dtype=torch.uint8, device=DEV)
+    Ad, lda = _colmajor(A)
+    Bd, ldb = _colmajor(B)
+
+    def call():
+        Cd = torch.full((n, m), 7.0, dtype=torch.float64, device=DEV)
+        rc = oz.ozaki2_dgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, 14, 0)
+        torch.cuda.synchronize()
+        return rc, Cd.cpu().numpy().T.copy()
+
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
     try:
+        assert oz.ozaki2_set_workspace(None, 0) == 0
+        rc, C = call()
+        assert rc == 2 and (C == 7.0).all()
         assert oz.ozaki2_set_workspace((small.data_ptr() + 255) // 256 * 256, need // 8) == 0
-        assert _bits_equal(_gpu_dgemm(A, B, 14), want)
+        rc, C = call()
+        assert rc == 2 and (C == 7.0).all()
+        assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_LIBRARY) == 0
+        rc, C = call()
+        assert rc == 0 and _bits_equal(C, want)
+        assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_CALLER) == 0
         assert oz.ozaki2_set_workspace((big.data_ptr() + 255) // 256 * 256, need) == 0
-        assert _bits_equal(_gpu_dgemm(A, B, 14), want)
+        rc, C = call()
+        assert rc == 0 and _bits_equal(C, want)
         assert oz.ozaki2_set_workspace(big.data_ptr() + 8, need) == -1   # misaligned
+        assert oz.ozaki2_set_workspace_policy(7) == -1
     finally:
-        oz.ozaki2_set_workspace(None, 0)
+        oz.ozaki2_set_workspace_policy(oz.WORKSPACE_CALLER)
+        oz.release_workspaces()
 
 
 @pytest.mark.parametrize("m,n,k,N,mode", [(6, 5, 2**17 + 5000, 14, 0), (3, 4, 2**18 + 77, 20, 1)])
@@ -340,6 +369,7 @@ def test_k_beyond_one_int32_block(m, n, k, N, mode):
     Ad, lda = _colmajor(A)
     Bd, ldb = _colmajor(B)
     Ct = torch.zeros(m * n, dtype=torch.int32, device=DEV)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, mode))
     rc = oz.ozaki2_debug_stages(m, n, k, Ad, lda, Bd, ldb, N, mode, 0,
                                 None, None, None, None, None, None, Ct)
     assert rc == 4   # OZ2_ERR_UNSUPPORTED
@@ -421,6 +451,7 @@ def test_exact_mode_sgemm_parity():
     Bd, ldb = _colmajor(B32)
     Cd = torch.zeros((n, m), dtype=torch.float32, device=DEV)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, 7, 3))
     assert oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, 7, 3) == 0
     torch.cuda.synchronize()
     got = Cd.cpu().numpy().T.copy()
@@ -482,6 +513,7 @@ def test_fused_sgemm_matches_unfused():
         Cd = torch.zeros((n, m), dtype=torch.float32, device=DEV)
         assert oz.ozaki2_set_tile(tile) == 0
         oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+        oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, 7, 0))
         assert oz.ozaki2_sgemm(m, n, k, Ad, lda, Bd, ldb, Cd, m, 7, 0) == 0
         torch.cuda.synchronize()
         oz.ozaki2_set_tile(0)

@@ -201,3 +201,45 @@ def test_accurate_rounding_boundary_is_exact_in_binary32():
     assert lo < exact < hi
     assert math.floor(_f32("429a5f11") - hi) == 67
     assert math.floor(_f32("429a5f11") - lo) == 68
+
+
+def _edge_rows(rng, rows, cols):
+    out = np.empty((rows, cols))
+    for i in range(rows):
+        kind = i % 4
+        if kind == 0:
+            out[i] = rng.standard_normal(cols) * np.exp(2 * rng.standard_normal(cols))
+        elif kind == 1:
+            out[i] = rng.standard_normal(cols) * 2.0 ** -1060     # scaled entries below normal
+            out[i, 0] = 2.0 ** -1000
+        elif kind == 2:
+            out[i] = rng.choice([0.0, 1.0, -3.0, 2.0 ** 500, 5e-324], cols)
+        else:
+            out[i] = 0.0
+    return out
+
+
+def test_accurate_bars_array_form_equals_scalar_form():
+    """The array form of accurate mode's first step (used for checks at full
+    size) gives the same exponents and bar matrices as ``accurate_log2``'s
+    entry-by-entry rational arithmetic, including zero rows, entries that
+    scale below the normal range and subnormal inputs."""
+    rng = np.random.default_rng(3)
+    A = _edge_rows(rng, 12, 9)
+    B = _edge_rows(rng, 8, 9).T.copy()          # columns carry the edge cases
+    emu, enu, Abar, Bbar, _ = scaling.accurate_log2(
+        A, B, constants.p_prime_accu(14), constants.delta())
+    e1, nz, bar = scaling.accurate_bars(A)
+    assert (bar == Abar).all()
+    assert (bar.max() <= 64) and (bar.min() >= 0)
+    e1b, nzb, barb = scaling.accurate_bars(B.T)
+    assert (barb.T == Bbar).all()
+    # exponents: recombine through the shared final step
+    Cbar = Abar @ Bbar
+    pa, d = constants.p_prime_accu(14), constants.delta()
+    got = [scaling.accurate_final_exponent(int(e1[i]) if nz[i] else None, int(Cbar[i].max()), pa, d)
+           for i in range(A.shape[0])]
+    assert got == emu
+    got = [scaling.accurate_final_exponent(int(e1b[j]) if nzb[j] else None, int(Cbar[:, j].max()),
+                                           pa, d) for j in range(B.shape[1])]
+    assert got == enu
