@@ -196,8 +196,10 @@ int ozaki2_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode,
 /* Use caller-owned device memory (256-byte aligned) as workspace for every
  * later call.  The library does not free it.  Pass (NULL, 0) to unset it.
  * The memory must stay valid until replaced and must not be in use by
- * another call in flight on another stream.  Returns 0, or -1 if ptr is not
- * 256-byte aligned. */
+ * another call in flight on another stream; between calls its contents
+ * belong to the library (ozaki2_dgemm_batched keeps tables there), so the
+ * caller does not write it.  Returns 0, or -1 if ptr is not 256-byte
+ * aligned. */
 int ozaki2_set_workspace(void* ptr, size_t bytes);
 
 /* What a call does when the caller's workspace is missing or too small.
@@ -309,10 +311,13 @@ typedef struct oz2_problem {
  * INT8 GEMMs of every problem and modulus run in one persistent kernel over
  * a shared work list.  k <= OZ2_K_BLOCK per problem.  The graph is built on
  * the first call with a given batch signature (shapes, N, mode, device,
- * workspace address; this call writes the batch's tables into the workspace
- * and synchronises) and replayed afterwards; a replay whose problems moved
- * to other matrices first rewrites those pointers with a small kernel
- * launch (the pointers travel as its arguments).  Every device buffer of
+ * workspace address and layout; this call writes the batch's tables into
+ * the workspace and synchronises) and replayed afterwards; a replay whose
+ * problems moved to other matrices first rewrites those pointers with a
+ * small kernel launch (the pointers travel as its arguments).  The tables
+ * stay in the workspace between calls: when any other call has used the
+ * workspace since, or a different workspace was set, they are written again
+ * (and the stream synchronised) before the replay.  Every device buffer of
  * the batch -- status, descriptors, work list, the phi estimate's scratch,
  * the per-problem regions -- lies in the caller's workspace, which must hold
  * ozaki2_dgemm_batched_workspace_size bytes (else OZ2_ERR_WORKSPACE, under

@@ -45,6 +45,11 @@ hipStream_t g_stream = nullptr;
 void* g_user_ws = nullptr;
 size_t g_user_ws_bytes = 0;
 int g_ws_policy = OZ2_WORKSPACE_CALLER;
+// Advanced whenever workspace memory may have been written by anything but
+// the batched path's own kernels (another entry point's call, a new or
+// re-set workspace, a library reallocation): the batch's tables, which stay
+// in the workspace between calls, are then written again before a replay.
+uint64_t g_ws_epoch = 1;
 ModTable g_host_tables[2][kMaxN + 1];
 bool g_host_tables_ok[2][kMaxN + 1];
 bool g_host_tables_built = false;
@@ -192,7 +197,11 @@ int ensure_device(int* dev_out) {
 // default policy (OZ2_WORKSPACE_CALLER), OZ2_ERR_WORKSPACE: no call on the
 // hot path allocates device memory.  Under OZ2_WORKSPACE_LIBRARY (an opt-in
 // convenience) the library allocates, grows and keeps its own.
-int get_workspace(int dev, size_t bytes, char** out) {
+// Every call advances g_ws_epoch except those of the batched path
+// (keeps_batch_tables), whose writes never reach the tables of a batch with
+// the same signature.
+int get_workspace(int dev, size_t bytes, char** out, bool keeps_batch_tables = false) {
+  if (!keeps_batch_tables) ++g_ws_epoch;
   if (g_user_ws && g_user_ws_bytes >= bytes) {
     *out = reinterpret_cast<char*>(g_user_ws);
     return 0;
@@ -200,6 +209,7 @@ int get_workspace(int dev, size_t bytes, char** out) {
   if (g_ws_policy != OZ2_WORKSPACE_LIBRARY) return OZ2_ERR_WORKSPACE;
   DevState& D = g_dev[dev];
   if (D.ws_bytes < bytes) {
+    ++g_ws_epoch;
     if (D.ws) {
       if (hipDeviceSynchronize() != hipSuccess) return OZ2_ERR_HIP;
       (void)hipFree(D.ws);
@@ -621,6 +631,7 @@ struct BatchState {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   std::vector<BatchProb> uploaded;  // descriptors as last written to the device
+  uint64_t epoch = 0;               // g_ws_epoch when the tables were written
 };
 BatchState g_batch;
 
@@ -769,7 +780,8 @@ int plan_batch(int batch, const oz2_problem* P, int mode, size_t tune_ops, Batch
     off += pl->lay[a].total;
   }
   pl->total = off;
-  pl->sig = sig;
+  // where the tables and regions sit (they move with the phi scratch)
+  pl->sig = mix64(mix64(sig, (uint64_t)pl->off_probs), (uint64_t)pl->total);
   return 0;
 }
 
@@ -878,7 +890,7 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, size_t tune_
   if ((rc = ensure_device(&dev))) return rc;
   DevState& D = g_dev[dev];
   char* ws = nullptr;
-  if (!pl.act.empty() && (rc = get_workspace(dev, pl.total, &ws))) return rc;
+  if (!pl.act.empty() && (rc = get_workspace(dev, pl.total, &ws, true))) return rc;
 
   for (int i = 0; i < batch; ++i) {
     const oz2_problem& q = P[i];
@@ -925,11 +937,10 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, size_t tune_
     B.k1a_gx = (q.m + 63) / 64;
   }
 
-  if (!g_batch.valid || g_batch.sig != sig) {
-    batch_release();
-    g_batch.uploaded.clear();
-    if (!g_batch.cap && hipStreamCreateWithFlags(&g_batch.cap, hipStreamNonBlocking) != hipSuccess)
-      return OZ2_ERR_HIP;
+  // Tables (descriptors, block prefixes and owners, work list): written in
+  // stream order after any earlier work on this workspace, and waited for
+  // (the host vectors are pageable memory).
+  auto upload_tables = [&]() -> int {
     std::vector<WorkItem> items = batch_items(P, pl);
     std::vector<uint16_t> owner((size_t)pl.total_blocks);
     for (int st = 0; st < kB_NSTAGES; ++st)
@@ -937,9 +948,6 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, size_t tune_
         for (int64_t bb = pl.prefix[(size_t)st * (na + 1) + a];
              bb < pl.prefix[(size_t)st * (na + 1) + a + 1]; ++bb)
           owner[(size_t)(pl.owner_off[st] + bb)] = (uint16_t)a;
-    // Tables of a new signature: written once, in stream order after any
-    // earlier work on this workspace, and waited for (the host vectors are
-    // pageable memory).
     if (hipMemcpyAsync(ws + pl.off_probs, probs.data(), sizeof(BatchProb) * na,
                        hipMemcpyHostToDevice, g_stream) != hipSuccess ||
         hipMemcpyAsync(ws + pl.off_prefix, pl.prefix.data(), pl.prefix.size() * sizeof(int64_t),
@@ -951,6 +959,16 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, size_t tune_
         hipStreamSynchronize(g_stream) != hipSuccess)
       return OZ2_ERR_HIP;
     g_batch.uploaded = probs;
+    g_batch.epoch = g_ws_epoch;
+    return 0;
+  };
+
+  if (!g_batch.valid || g_batch.sig != sig) {
+    batch_release();
+    g_batch.uploaded.clear();
+    if (!g_batch.cap && hipStreamCreateWithFlags(&g_batch.cap, hipStreamNonBlocking) != hipSuccess)
+      return OZ2_ERR_HIP;
+    if ((rc = upload_tables())) return rc;
     hipStream_t cs = g_batch.cap;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return OZ2_ERR_HIP;
@@ -963,9 +981,15 @@ int run_batched_resolved(int batch, const oz2_problem* P, int mode, size_t tune_
     g_batch.dev = dev;
     g_batch.ws = ws;
     g_batch.valid = true;
+  } else if (g_batch.epoch != g_ws_epoch) {
+    // Same signature, but the workspace was used by other calls since the
+    // tables were written (their regions overlap the tables): write them
+    // again; the captured graph addresses the same places.
+    if ((rc = upload_tables())) return rc;
   } else {
-    // Same signature: refresh the caller pointers that changed, in chunks
-    // carried as kernel arguments (stream ordered after the previous replay).
+    // Same signature and untouched tables: refresh the caller pointers that
+    // changed, in chunks carried as kernel arguments (stream ordered after
+    // the previous replay).
     BatchPtrs chunk;
     for (int a0 = 0; a0 < na; a0 += kBatchPtrChunk) {
       const int cnt = std::min(kBatchPtrChunk, na - a0);
@@ -1050,7 +1074,8 @@ int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode, double targ
     int dev;
     if ((rc = ensure_device(&dev))) return rc;
     char* ws = nullptr;
-    if ((rc = get_workspace(dev, bound.total, &ws))) return rc;
+    // the phi scratch ends where this plan's tables begin
+    if ((rc = get_workspace(dev, bound.total, &ws, true))) return rc;
     std::vector<double> phis;
     if ((rc = estimate_phis(ws + bound.off_tune, srcs, &phis))) return rc;
     for (size_t w = 0; w < who.size(); ++w)
@@ -1154,6 +1179,7 @@ int ozaki2_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode, size
 
 int ozaki2_set_workspace(void* ptr, size_t bytes) {
   if (reinterpret_cast<uintptr_t>(ptr) & 255) return -1;
+  if (ptr != g_user_ws || (ptr ? bytes : 0) != g_user_ws_bytes) ++g_ws_epoch;
   g_user_ws = ptr;
   g_user_ws_bytes = ptr ? bytes : 0;
   return 0;

@@ -68,6 +68,27 @@ def test_batched_replay_with_new_data_and_edge_problems():
                           _bits(oz.dgemm(*pairs[0], N=Ns[0]).cpu().numpy()))
 
 
+def test_batched_autotuned_then_given_N_same_shapes():
+    """The same shapes first with N = 0 (the autotuner's phi scratch moves the
+    batch's tables further into the workspace) and then with the N it chose:
+    the second call is a different plan and must write its own outputs,
+    bit-identical to the first call's and to single calls; a batch call
+    after single calls (which reuse the workspace) still gives the same
+    bits."""
+    probs = _problems(5, 10)
+    pairs = [(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)) for A, B, _ in probs]
+    outs1, Ns = oz.dgemm_batched(pairs, 0, target=1e-15, return_N=True)
+    outs2 = oz.dgemm_batched(pairs, Ns)
+    torch.cuda.synchronize()
+    singles = [oz.dgemm(a, b, N=N).cpu().numpy() for (a, b), N in zip(pairs, Ns)]
+    outs3 = oz.dgemm_batched(pairs, Ns)
+    torch.cuda.synchronize()
+    for c1, c2, c3, s in zip(outs1, outs2, outs3, singles):
+        assert np.array_equal(_bits(c1.cpu().numpy()), _bits(s))
+        assert np.array_equal(_bits(c2.cpu().numpy()), _bits(s))
+        assert np.array_equal(_bits(c3.cpu().numpy()), _bits(s))
+
+
 def test_batched_large_ragged_problems_equal_single_calls():
     """Problems up to 1500 x 1100 (many tiles per plane, split over XCDs by the
     work ordering) next to small ones, ragged in every dimension: every
