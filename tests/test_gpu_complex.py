@@ -42,6 +42,8 @@ def _gpu(A, B, N, mode=0, lda=None, ldb=None, ldc=None, single=False):
                     device=DEV)
     oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
     fn = oz.ozaki2_cgemm if single else oz.ozaki2_zgemm
+    if mode != 2:
+        oz.ensure_workspace(oz.ozaki2_zgemm_workspace_size(m, n, k, N, mode))
     print(f"{fn.__name__} m={m} n={n} k={k} N={N} mode={mode}", flush=True)
     rc = fn(m, n, k, Ad, lda, Bd, ldb, Cd, ldc, N, mode)
     assert rc == 0, oz.ozaki2_status_string(rc)
