@@ -66,6 +66,8 @@ extern "C" {
 #define OZ2_ERR_HIP          3 /* a HIP runtime call failed */
 #define OZ2_ERR_UNSUPPORTED  4 /* valid request this build does not support */
 #define OZ2_ERR_TOO_LARGE    5 /* a size overflows the library's indexing */
+#define OZ2_ERR_SCRATCH_TOO_SMALL 6 /* ozaki2_dgemm_noalloc: the problem needs
+                                       more than OZ2_NOALLOC_SCRATCH_BYTES */
 
 /* Device status bits reported by ozaki2_get_device_status. */
 #define OZ2_STATUS_NONFINITE 1 /* a row/column had a NaN/Inf entry or (other
@@ -122,6 +124,31 @@ int ozaki2_dgemm(int64_t m, int64_t n, int64_t k,
                  const double* B, int64_t ldb,
                  double* C, int64_t ldc,
                  int N, int mode);
+
+/*
+ * ozaki2_dgemm_noalloc -- ozaki2_dgemm for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * device allocation).  Same arguments, results (bit for bit), stream and
+ * return codes as ozaki2_dgemm, but the workspace is a fixed device array of
+ * OZ2_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until the
+ * process ends) instead of the memory set by ozaki2_set_workspace; the call
+ * allocates nothing (no hipMalloc, no library allocation, no events) and
+ * launches only kernels (no memset), so it may be captured into a graph.
+ * The caller still passes A, B and C.  A problem whose workspace would
+ * exceed the array returns OZ2_ERR_SCRATCH_TOO_SMALL and launches nothing;
+ * every problem with ozaki2_workspace_size <= OZ2_NOALLOC_SCRATCH_BYTES is
+ * accepted (the check uses the layout of the GEMM tile the call picks,
+ * which may accept somewhat larger ones), e.g. m = n = k = 1024 at any N.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams, or different host threads) race and must be
+ * ordered by the caller.  Stage timing (ozaki2_set_timing) does not apply.
+ */
+#define OZ2_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ozaki2_dgemm_noalloc(int64_t m, int64_t n, int64_t k,
+                         const double* A, int64_t lda,
+                         const double* B, int64_t ldb,
+                         double* C, int64_t ldc,
+                         int N, int mode);
 
 /*
  * ozaki2_sgemm -- as ozaki2_dgemm for binary32 A, B and C (Section 5 applies

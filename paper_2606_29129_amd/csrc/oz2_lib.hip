@@ -28,6 +28,12 @@ using namespace oz2;
 // Constant tables for every N (index 0: fast modes, 1: accurate mode limbs).
 __device__ ModTable g_tables[2][kMaxN + 1];
 
+// Workspace of ozaki2_dgemm_noalloc: fixed device memory, one copy per GPU
+// (held until the process ends).  Host code never passes `scratch` itself
+// (on the host it names a stand-in, not device memory); it uses the device
+// address taken once per device with hipGetSymbolAddress (DevState).
+static __device__ __align__(256) char scratch[OZ2_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int kBM = 256, kBN = 256, kBK = 128;  // largest K3 tile (sizes the workspace)
@@ -38,6 +44,7 @@ struct DevState {
   ModTable* d_tables = nullptr;  // device address of g_tables
   void* ws = nullptr;            // library-owned workspace (OZ2_WORKSPACE_LIBRARY only)
   size_t ws_bytes = 0;
+  char* scratch = nullptr;       // device address of `scratch` on this device
 };
 
 DevState g_dev[kMaxDevices];
@@ -187,6 +194,9 @@ int ensure_device(int* dev_out) {
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_tables)) != hipSuccess) return OZ2_ERR_HIP;
     D.d_tables = reinterpret_cast<ModTable*>(p);
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) return OZ2_ERR_HIP;
+    D.scratch = reinterpret_cast<char*>(sp);
     D.ready = true;
   }
   *dev_out = dev;
@@ -238,7 +248,7 @@ std::vector<TimedCall> g_free;
 struct StageClock {
   bool on;
   TimedCall tc;
-  StageClock() : on(g_timing != 0) {
+  explicit StageClock(bool allowed = true) : on(allowed && g_timing != 0) {
     if (!on) return;
     if (!g_free.empty()) {
       tc = g_free.back();
@@ -323,9 +333,13 @@ void launch_crt(const Layout& L, char* ws, const ModTable* tab, int N, int64_t m
       tab, N, m, n, L.Mp, L.Np, C, ldc);
 }
 
+// fixed_ws: the device's `scratch` array as the workspace (no stage events,
+// no allocation of any kind); a call that needs more returns
+// OZ2_ERR_SCRATCH_TOO_SMALL before launching anything.
 template <typename T, typename TO>
 int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
-             int64_t ldb, TO* C, int64_t ldc, int N, int mode, const Debug* dbg) {
+             int64_t ldb, TO* C, int64_t ldc, int N, int mode, const Debug* dbg,
+             bool fixed_ws = false) {
   int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, N, mode, dbg == nullptr);
   if (rc) return rc;
   if (dbg && (dbg->t < 0 || dbg->t >= N)) return -10;
@@ -354,9 +368,14 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   Layout L = fused ? make_layout(m, n, k, N, mode, kFuseRows, kFuseCols, 1, true)
                    : make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg]);
   char* ws = nullptr;
-  if ((rc = get_workspace(dev, L.total, &ws))) return rc;
+  if (fixed_ws) {
+    if (L.total > (size_t)OZ2_NOALLOC_SCRATCH_BYTES) return OZ2_ERR_SCRATCH_TOO_SMALL;
+    ws = D.scratch;
+  } else if ((rc = get_workspace(dev, L.total, &ws))) {
+    return rc;
+  }
 
-  StageClock clk;
+  StageClock clk(!fixed_ws);
   clk.mark(0);
   // K1: squared norms and exponents.
   k_clear_status<<<1, 64, 0, g_stream>>>((int*)(ws + L.status));
@@ -1137,6 +1156,11 @@ int ozaki2_dgemm(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
   return run_gemm<double, double>(m, n, k, A, lda, B, ldb, C, ldc, N, mode, nullptr);
 }
 
+int ozaki2_dgemm_noalloc(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, double* C, int64_t ldc, int N, int mode) {
+  return run_gemm<double, double>(m, n, k, A, lda, B, ldb, C, ldc, N, mode, nullptr, true);
+}
+
 int ozaki2_sgemm(int64_t m, int64_t n, int64_t k, const float* A, int64_t lda,
                  const float* B, int64_t ldb, float* C, int64_t ldc, int N, int mode) {
   return run_gemm<float, float>(m, n, k, A, lda, B, ldb, C, ldc, N, mode, nullptr);
@@ -1199,8 +1223,8 @@ int ozaki2_get_device_status(int* status) {
   *status = 0;
   if (hipStreamSynchronize(g_stream) != hipSuccess) return OZ2_ERR_HIP;
   // The status word lives at offset 0 of whichever workspace the last call
-  // used; both candidates are checked and cleared.
-  void* cands[2] = {g_user_ws, g_dev[dev].ws};
+  // used; every candidate is checked and cleared.
+  void* cands[3] = {g_user_ws, g_dev[dev].ws, g_dev[dev].scratch};
   for (void* p : cands) {
     if (!p) continue;
     int v = 0;
@@ -1223,6 +1247,9 @@ const char* ozaki2_status_string(int code) {
     case OZ2_ERR_HIP: return "HIP runtime error";
     case OZ2_ERR_UNSUPPORTED: return "unsupported request";
     case OZ2_ERR_TOO_LARGE: return "problem size too large";
+    case OZ2_ERR_SCRATCH_TOO_SMALL:
+      return "ozaki2_dgemm_noalloc: the problem needs more workspace than the library's fixed "
+             "device scratch (OZ2_NOALLOC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }

@@ -36,6 +36,8 @@ class Oz2Problem(ctypes.Structure):
 
 _SIGS = {
     "ozaki2_dgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
+    "ozaki2_dgemm_noalloc": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int],
+                             _c_int),
     "ozaki2_sgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
     "ozaki2_zgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
     "ozaki2_cgemm": ([_c_i64] * 3 + [_vp, _c_i64, _vp, _c_i64, _vp, _c_i64, _c_int, _c_int], _c_int),
@@ -109,6 +111,10 @@ def _check(fn, rc):
 
 def ozaki2_dgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
     return lib().ozaki2_dgemm(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
+
+
+def ozaki2_dgemm_noalloc(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):
+    return lib().ozaki2_dgemm_noalloc(m, n, k, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, N, mode)
 
 
 def ozaki2_sgemm(m, n, k, A, lda, B, ldb, C, ldc, N, mode=MODE_REVISED):

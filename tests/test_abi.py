@@ -50,6 +50,7 @@ def test_library_exports_every_declared_symbol():
 def test_argument_errors_are_reported_without_device_work(args, code):
     assert oz.ozaki2_dgemm(*args) == code
     assert oz.ozaki2_sgemm(*args) == code
+    assert oz.ozaki2_dgemm_noalloc(*args) == code
 
 
 def test_quick_returns_need_no_device():
