@@ -55,6 +55,23 @@ extern "C" {
  * overflows (two extra launches that exit at once). */
 #define OZ2_MODE_EXACT    3
 
+/* Engine flag, or-ed into the mode of ozaki2_dgemm, ozaki2_sgemm,
+ * ozaki2_workspace_size and ozaki2_debug_stages: the residue products of
+ * Step 3 run on the FP8 (E4M3) matrix engine instead of the INT8 one.  The
+ * paper states that its scaling serves Ozaki scheme II on FP8 engines too
+ * (Section 1) and leaves that extension open (Section 6).  Everything but
+ * the products is the INT8 path's (scaling, integers, residues, CRT,
+ * unscaling); each residue r is split as r = 16 h + l (l in [-8, 7]) into
+ * two E4M3 operands, 16 h and l, the four digit products of an index are
+ * summed in binary32 -- exactly, since 512 indices keep every partial sum
+ * below 2^24 -- and each block of 512 indices is added in INT32.  The
+ * products, and so C, are bit-identical to the INT8 path's; the engine does
+ * four times the INT8 path's MFMA work.  Fast modes only (with
+ * OZ2_MODE_ACCURATE the call returns OZ2_ERR_UNSUPPORTED).  The workspace
+ * holds two digit planes per modulus and operand besides the INT8 ones
+ * (ozaki2_workspace_size with the flag reports it). */
+#define OZ2_ENGINE_FP8    16
+
 /* Status codes (positive; argument errors are negative). */
 #define OZ2_SUCCESS          0
 #define OZ2_ERR_K_TOO_LARGE  1 /* k above OZ2_K_MAX (OZ2_K_MAX_ACCURATE in

@@ -121,6 +121,114 @@ __device__ __forceinline__ void wait_vmem_lds_all() {
 #endif
 }
 
+// The epilogue of a BM x BN tile whose wave (wm, wn) holds the exact INT32
+// products of its (BM/2) x (BN/2) part in acc (TM x TN blocks of 32 x 32 in
+// the MFMA accumulator layout): EPI 0 stores U_t = C_t mod p_t, EPI 1 the raw
+// product, EPI 2 folds it into row and column maxima, EPI 3 adds C_t mod p_t
+// to U_t (see the top of this file).
+template <int BM, int BN, int EPI>
+__device__ __forceinline__ void tile_epilogue(
+    const v16i (&acc)[BM / 64][BN / 64], uint8_t* __restrict__ U, int32_t* __restrict__ aux0,
+    int32_t* __restrict__ aux1, int64_t m, int64_t n, int64_t Mp, int64_t Np,
+    const ModTable* __restrict__ tab, int t, int tm, int tn, int wm, int wn, int lane) {
+  constexpr int TM = BM / 64, TN = BN / 64;
+  const int64_t Mb = Mp / 32;
+  if constexpr (EPI == 1) {
+    int32_t* Craw = aux0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t col = (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane);
+          if (row < m && col < n) Craw[row + col * m] = acc[i][j][r];
+        }
+      }
+    return;
+  }
+  if constexpr (EPI == 2) {
+    int32_t* rmax = aux0;   // per row of the product (Mp entries)
+    int32_t* cmax = aux1;   // per column (Np entries)
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int v = acc[i][0][r];
+#pragma unroll
+        for (int j = 1; j < TN; ++j) v = v > acc[i][j][r] ? v : acc[i][j][r];
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+          int u = __shfl_xor(v, o);
+          v = v > u ? v : u;
+        }
+        if ((lane & 31) == 0)
+          atomicMax(rmax + (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane), v);
+      }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      int v = acc[0][j][0];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v = v > acc[i][j][r] ? v : acc[i][j][r];
+      int u = __shfl_xor(v, 32);
+      v = v > u ? v : u;
+      if (lane < 32) atomicMax(cmax + (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane), v);
+    }
+    return;
+  }
+  const int64_t Nb = Np / 32;
+  const bool is256 = (t == 0);
+  const double p = tab->p[t], ip = tab->inv_p[t];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int c = acc[i][j][4 * q + e];
+          uint32_t u;
+          if (is256) {
+            u = (uint32_t)c & 0xFFu;
+          } else {
+            double y = (double)c;
+            double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
+            u = (uint32_t)(int)(r < 0.0 ? r + p : r);
+          }
+          b |= u << (8 * e);
+        }
+        w[q] = b;
+      }
+      const int64_t bi = (int64_t)tm * (BM / 32) + wm * (TM) + i;
+      const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;
+      uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
+      if constexpr (EPI == 3) {
+        // a later k block: U = (U + C mod p) mod p, byte by byte
+        const uint4 o = *reinterpret_cast<const uint4*>(dst);
+        const uint32_t ow[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t pu = (uint32_t)p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t b = 0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            uint32_t v = ((ow[q] >> (8 * e)) & 0xFFu) + ((w[q] >> (8 * e)) & 0xFFu);
+            v = is256 ? (v & 0xFFu) : (v >= pu ? v - pu : v);
+            b |= v << (8 * e);
+          }
+          w[q] = b;
+        }
+      }
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 // One BM x BN output tile of plane t (tile row tm, tile column tn).
 //
 // Main loop: one BK-byte k slab per iteration (128 bytes for the plain tiles,
@@ -305,101 +413,7 @@ __device__ __forceinline__ void gemm_tile(
   slab(nk - 1, std::false_type{}, std::false_type{});
   wait_vmem_all();  // no load may still target LDS when the tile returns
 
-  const int64_t Mb = Mp / 32;
-  if constexpr (EPI == 1) {
-    int32_t* Craw = aux0;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int64_t col = (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t row = (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane);
-          if (row < m && col < n) Craw[row + col * m] = acc[i][j][r];
-        }
-      }
-    return;
-  }
-  if constexpr (EPI == 2) {
-    int32_t* rmax = aux0;   // per row of the product (Mp entries)
-    int32_t* cmax = aux1;   // per column (Np entries)
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        int v = acc[i][0][r];
-#pragma unroll
-        for (int j = 1; j < TN; ++j) v = v > acc[i][j][r] ? v : acc[i][j][r];
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-          int u = __shfl_xor(v, o);
-          v = v > u ? v : u;
-        }
-        if ((lane & 31) == 0)
-          atomicMax(rmax + (int64_t)tm * BM + wm * (BM / 2) + i * 32 + acc_row(r, lane), v);
-      }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      int v = acc[0][j][0];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v = v > acc[i][j][r] ? v : acc[i][j][r];
-      int u = __shfl_xor(v, 32);
-      v = v > u ? v : u;
-      if (lane < 32) atomicMax(cmax + (int64_t)tn * BN + wn * (BN / 2) + j * 32 + acc_col(lane), v);
-    }
-    return;
-  }
-  const int64_t Nb = Np / 32;
-  const bool is256 = (t == 0);
-  const double p = tab->p[t], ip = tab->inv_p[t];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      uint32_t w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t b = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int c = acc[i][j][4 * q + e];
-          uint32_t u;
-          if (is256) {
-            u = (uint32_t)c & 0xFFu;
-          } else {
-            double y = (double)c;
-            double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
-            u = (uint32_t)(int)(r < 0.0 ? r + p : r);
-          }
-          b |= u << (8 * e);
-        }
-        w[q] = b;
-      }
-      const int64_t bi = (int64_t)tm * (BM / 32) + wm * (TM) + i;
-      const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;
-      uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
-      if constexpr (EPI == 3) {
-        // a later k block: U = (U + C mod p) mod p, byte by byte
-        const uint4 o = *reinterpret_cast<const uint4*>(dst);
-        const uint32_t ow[4] = {o.x, o.y, o.z, o.w};
-        const uint32_t pu = (uint32_t)p;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          uint32_t b = 0;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            uint32_t v = ((ow[q] >> (8 * e)) & 0xFFu) + ((w[q] >> (8 * e)) & 0xFFu);
-            v = is256 ? (v & 0xFFu) : (v >= pu ? v - pu : v);
-            b |= v << (8 * e);
-          }
-          w[q] = b;
-        }
-      }
-      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
-    }
+  tile_epilogue<BM, BN, EPI>(acc, U, aux0, aux1, m, n, Mp, Np, tab, t, tm, tn, wm, wn, lane);
 }
 
 template <int BM, int BN, int BK, int EPI>

@@ -14,6 +14,7 @@
 #include "oz2_k1_norm.hpp"
 #include "oz2_k2_split.hpp"
 #include "oz2_k3_gemm.hpp"
+#include "oz2_k3_fp8.hpp"
 #include "oz2_k4_crt.hpp"
 #include "oz2_tables.hpp"
 #include "oz2_batched.hpp"
@@ -79,6 +80,7 @@ struct Layout {
   int64_t Mp, Np, Kp, nch;
   size_t eA, eB, SA, SB, partA, partB, maxA, maxB, RA, RB, U, status, total;
   size_t e1A, e1B, cmaxA, cmaxB, barA, barB;  // accurate mode only
+  size_t FA, FB;                               // FP8 engine: digit planes
 };
 
 // GEMM tile configurations (OZ2_TILE_*): rows x columns of the output tile.
@@ -125,6 +127,8 @@ int tile_config(int64_t m, int64_t n, int64_t k, int N) {
 // norms run over 2k components).
 Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm = kBM,
                    int64_t bn = kBN, int comps = 1, bool fused = false) {
+  const bool fp8 = (mode & OZ2_ENGINE_FP8) != 0;
+  mode &= ~OZ2_ENGINE_FP8;
   Layout L;
   L.Mp = round_up(m > 0 ? m : 1, bm);
   L.Np = round_up(n > 0 ? n : 1, bn);
@@ -153,6 +157,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t k, int N, int mode, int64_t bm 
   L.RA = take(fused ? 0 : (size_t)comps * N * L.Mp * L.Kp);
   L.RB = take((size_t)comps * N * L.Np * L.Kp);
   L.U = take(fused ? 0 : (size_t)comps * N * L.Mp * L.Np);
+  L.FA = fp8 ? take((size_t)N * L.Mp * 2 * L.Kp) : 0;
+  L.FB = fp8 ? take((size_t)N * L.Np * 2 * L.Kp) : 0;
   L.total = off;
   return L;
 }
@@ -173,6 +179,7 @@ int check_args(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
     if (ldc < (m > 1 ? m : 1)) return -9;
   }
   if (N < OZ2_N_MIN || N > OZ2_N_MAX) return -10;
+  mode &= ~OZ2_ENGINE_FP8;
   if (mode != OZ2_MODE_REVISED && mode != OZ2_MODE_ORIGINAL && mode != OZ2_MODE_ACCURATE &&
       mode != OZ2_MODE_EXACT)
     return -11;
@@ -344,6 +351,9 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   if (rc) return rc;
   if (dbg && (dbg->t < 0 || dbg->t >= N)) return -10;
   if (dbg && dbg->Ct && k > OZ2_K_BLOCK) return OZ2_ERR_UNSUPPORTED;  // INT32 of one block
+  const bool fp8 = (mode & OZ2_ENGINE_FP8) != 0;
+  mode &= ~OZ2_ENGINE_FP8;
+  if (fp8 && mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
   if (m == 0 || n == 0) return 0;
   int dev;
   if ((rc = ensure_device(&dev))) return rc;
@@ -362,10 +372,11 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   const int cfg = tile_config(m, n, k, N);
   // Narrow B: conversion of A, products and CRT in one kernel (automatic
   // tile choice only; a forced tile keeps the separate kernels).
-  const bool fused = !dbg && g_tile_policy == OZ2_TILE_AUTO && n <= kFuseCols &&
+  const bool fused = !dbg && !fp8 && g_tile_policy == OZ2_TILE_AUTO && n <= kFuseCols &&
                      N <= kFuseMaxN && mode != OZ2_MODE_ACCURATE && k <= OZ2_K_BLOCK &&
                      HT.limbs == 2;
   Layout L = fused ? make_layout(m, n, k, N, mode, kFuseRows, kFuseCols, 1, true)
+             : fp8 ? make_layout(m, n, k, N, mode | OZ2_ENGINE_FP8, kF8Tile, kF8Tile)
                    : make_layout(m, n, k, N, mode, kTileBM[cfg], kTileBN[cfg]);
   char* ws = nullptr;
   if (fixed_ws) {
@@ -479,9 +490,36 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
     case 3: launch_split<T, 3>(A, lda, B, ldb, m, n, k, L, ws, tab, N); break;
     default: launch_split<T, 4>(A, lda, B, ldb, m, n, k, L, ws, tab, N); break;
   }
+  if (fp8) {
+    // the two E4M3 digit planes of every residue plane
+    const int64_t ga = N * L.Mp * (L.Kp / 16), gb = N * L.Np * (L.Kp / 16);
+    k_fp8_digits<<<(unsigned)((ga + 255) / 256), 256, 0, g_stream>>>(
+        (const int8_t*)(ws + L.RA), (uint8_t*)(ws + L.FA), N * L.Mp, L.Kp);
+    k_fp8_digits<<<(unsigned)((gb + 255) / 256), 256, 0, g_stream>>>(
+        (const int8_t*)(ws + L.RB), (uint8_t*)(ws + L.FB), N * L.Np, L.Kp);
+  }
   clk.mark(2);
-  // K3: N INT8 GEMMs.
-  if (dbg) {
+  // K3: N residue products (INT8 engine, or the FP8 one).
+  if (fp8) {
+    const uint8_t* FA = (const uint8_t*)(ws + L.FA);
+    const uint8_t* FB = (const uint8_t*)(ws + L.FB);
+    const unsigned tiles = (unsigned)((L.Mp / kF8Tile) * (L.Np / kF8Tile));
+    if (dbg) {
+      if (dbg->Ct)
+        k3_gemm_f8<1><<<tiles, 256, 0, g_stream>>>(FA, FB, nullptr, dbg->Ct, m, n, L.Mp, L.Np,
+                                                   L.Kp, tab, dbg->t, 0, L.Kp);
+    } else {
+      for (int64_t k0 = 0; k0 < L.Kp; k0 += OZ2_K_BLOCK) {
+        const int64_t klen = std::min<int64_t>(OZ2_K_BLOCK, L.Kp - k0);
+        if (k0 == 0)
+          k3_gemm_f8<0><<<tiles * N, 256, 0, g_stream>>>(FA, FB, (uint8_t*)(ws + L.U), nullptr,
+                                                         m, n, L.Mp, L.Np, L.Kp, tab, 0, k0, klen);
+        else
+          k3_gemm_f8<3><<<tiles * N, 256, 0, g_stream>>>(FA, FB, (uint8_t*)(ws + L.U), nullptr,
+                                                         m, n, L.Mp, L.Np, L.Kp, tab, 0, k0, klen);
+      }
+    }
+  } else if (dbg) {
     if (dbg->Ct)
       launch_gemm<1>(cfg, (const int8_t*)(ws + L.RA), (const int8_t*)(ws + L.RB), nullptr,
                      dbg->Ct, nullptr, m, n, L, tab, dbg->t, 1);
@@ -531,7 +569,7 @@ int run_complex(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const 
                 int64_t ldb, T* C, int64_t ldc, int N, int mode) {
   int rc = check_args(m, n, k, A, lda, B, ldb, C, ldc, N, mode, true);
   if (rc) return rc;
-  if (mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
+  if (mode == OZ2_MODE_ACCURATE || (mode & OZ2_ENGINE_FP8)) return OZ2_ERR_UNSUPPORTED;
   const uintptr_t align = 2 * sizeof(T) - 1;   // one complex entry
   if (reinterpret_cast<uintptr_t>(A) & align) return -4;
   if (reinterpret_cast<uintptr_t>(B) & align) return -6;
@@ -1181,7 +1219,7 @@ int ozaki2_zgemm_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode
   int rc = check_args(m, n, k, (const void*)16, m > 1 ? m : 1, (const void*)16, k > 1 ? k : 1,
                       (const void*)16, m > 1 ? m : 1, N, mode, true);
   if (rc) return rc;
-  if (mode == OZ2_MODE_ACCURATE) return OZ2_ERR_UNSUPPORTED;
+  if (mode == OZ2_MODE_ACCURATE || (mode & OZ2_ENGINE_FP8)) return OZ2_ERR_UNSUPPORTED;
   if (!bytes) return -6;
   *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(m, n, k, N, mode, kBM, kBN, 3).total;
   return 0;
@@ -1197,6 +1235,9 @@ int ozaki2_workspace_size(int64_t m, int64_t n, int64_t k, int N, int mode, size
                       (const void*)1, m > 1 ? m : 1, N, mode, true);
   if (rc) return rc;
   if (!bytes) return -6;
+  if ((mode & OZ2_ENGINE_FP8) && (mode & ~OZ2_ENGINE_FP8) == OZ2_MODE_ACCURATE)
+    return OZ2_ERR_UNSUPPORTED;
+  // the largest tile's padding: an upper bound for every tile the call may pick
   *bytes = (m == 0 || n == 0 || k == 0) ? 0 : make_layout(m, n, k, N, mode).total;
   return 0;
 }
@@ -1255,8 +1296,9 @@ const char* ozaki2_status_string(int code) {
 }
 
 const char* ozaki2_version(void) {
-  return "ozaki2 0.2 gfx950 kc=64 slice=39 limb=40 log2=rn32(log2_f64) "
-         "tiles=256x256x128,128x128x128,256x64x128(auto) batched=128x128x128";
+  return "ozaki2 0.3 gfx950 kc=64 slice=39 limb=40 log2=rn32(log2_f64) "
+         "tiles=256x256x128,128x128x128,256x64x128(auto) batched=128x128x128 "
+         "fp8=e4m3x2digits,128x128x64,kb512";
 }
 
 int ozaki2_finalize(void) {

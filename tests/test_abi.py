@@ -195,3 +195,20 @@ def test_workspace_policy_values():
     assert oz.ozaki2_set_workspace_policy(2) == -1
     assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_LIBRARY) == 0
     assert oz.ozaki2_set_workspace_policy(oz.WORKSPACE_CALLER) == 0
+
+
+def test_fp8_engine_flag_on_the_host():
+    """OZ2_ENGINE_FP8 (16) or-ed into the mode: the workspace grows by the two
+    E4M3 digit planes per modulus and operand; accurate mode with the flag is
+    unsupported (4); an unknown base mode with the flag is still argument 11."""
+    m, n, k, N = 300, 200, 500, 14
+    base = oz.ozaki2_workspace_size(m, n, k, N, 0)
+    with8 = oz.ozaki2_workspace_size(m, n, k, N, 16)
+    pad = lambda x: (x + 255) // 256 * 256
+    assert with8 - base >= 2 * N * (pad(m) + pad(n)) * pad(k)
+    for mode in (1, 3):
+        assert oz.ozaki2_workspace_size(m, n, k, N, mode | 16) > oz.ozaki2_workspace_size(m, n, k, N, mode)
+    b = ctypes.c_size_t(0)
+    assert oz.lib().ozaki2_workspace_size(m, n, k, N, 2 | 16, ctypes.byref(b)) == 4
+    assert oz.ozaki2_dgemm(4, 4, 4, 1, 4, 1, 4, 1, 4, 14, 4 | 16) == -11
+    assert oz.ozaki2_dgemm(4, 4, 4, 1, 4, 1, 4, 1, 4, 21, 16) == -10
