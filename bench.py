@@ -33,7 +33,9 @@ The same JSON line carries:
                   graph launch against one call per problem, per-stage times
                   of the same kernels launched directly, the INT8 rate of
                   the persistent GEMM and native FP64 on the same problems;
-  complex         ZGEMM at 8192^3 beside native complex128 matmul.
+  complex         ZGEMM at 8192^3 beside native complex128 matmul;
+  fp8_engine      the FP8 (E4M3) engine variant at 8192^3 beside the INT8
+                  engine (bit-identical C, engine rate vs the FP8 peak).
 """
 from __future__ import annotations
 
@@ -48,6 +50,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_PEAK_TOPS = 5000.0      # MI355X dense INT8 MFMA, 5.0 POP/s
+FP8_PEAK_TFLOPS = 5000.0     # MI355X dense FP8 MFMA, 5.0 PFLOP/s
+FP8_FLAG = 16                # OZ2_ENGINE_FP8
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k3_gemm_i8_traffic.txt")
 K3_SOURCE = os.path.join(ROOT, "paper_2606_29129_amd", "csrc", "oz2_k3_gemm.hpp")
 MODES = {"revised": 0, "original": 1, "accurate": 2, "exact": 3}
@@ -156,24 +160,21 @@ def block_errors(C_cm, blk):
     return dict(max_rel_err=e["max_rel"], max_cw_err=e["max_cw"], zero_ref_nonzero=e["zero_ref_nonzero"])
 
 
-def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0):
-    """Time the CPU oracle computing sampled entries of the same product from
-    scratch (row and column norms, exponents, residues, N dot products, CRT,
-    unscaling), and check the GPU's entries against it bit for bit."""
+def _oracle_entries(rows_path, cols_path, pairs, N, mode, budget_s):
+    """Worker of cpu_baseline (a process of its own): the oracle's entries
+    for the (row, column) index pairs in order until the time budget is
+    spent.  Returns [(pair index, C_ij)] and the seconds spent computing."""
     import numpy as np
     from oracle import constants, ozaki2 as ref, scaling
-
-    m, k = A_rm.shape
-    n = B_rm.shape[1]
-    rng = np.random.default_rng(seed)
+    R = np.load(rows_path, mmap_mode="r")
+    Q = np.load(cols_path, mmap_mode="r")
     pp = constants.p_prime_prop(N)
     pf, d = constants.p_prime_fast(N), constants.delta()
-    done = exact_ok = 0
-    elapsed = 0.0
-    while elapsed < budget_s or done < 2:
-        i, j = int(rng.integers(m)), int(rng.integers(n))
-        row = A_rm[i].double().cpu().numpy()
-        col = B_rm[:, j].double().cpu().numpy()
+    out, spent = [], 0.0
+    for idx, (r, c) in pairs:
+        if spent >= budget_s and out:
+            break
+        row, col = np.array(R[r]), np.array(Q[c])
         t0 = time.perf_counter()
         Si, Sj = scaling.norm_sq_ru(row), scaling.norm_sq_ru(col)
         if mode == 0:
@@ -185,17 +186,71 @@ def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0):
         else:
             ei = scaling.alg1_log2_mu(Si, float(np.max(np.abs(row))), pf, d)
             fj = scaling.alg1_log2_mu(Sj, float(np.max(np.abs(col))), pf, d)
-        c, _, _ = ref.entry(row, col, ei, fj, N)
-        elapsed += time.perf_counter() - t0
-        g = float(C_cm[j, i])
-        exact_ok += int(np.float64(g).view(np.uint64) == np.float64(c).view(np.uint64))
-        done += 1
-    return dict(value=2.0 * k * done / elapsed / 1e12, unit="TFLOPS", cores=1, kind="oracle",
-                sample=f"{done} entries C_ij of this workload at seeded random (i, j), each "
-                       f"computed from scratch from its full row of A and column of B "
-                       f"(k={k}, N={N}): 2k flops credited per entry",
-                seconds=round(elapsed, 2), threads="1 (pure Python integers)",
-                **host_cpu()), done, exact_ok
+        c_ij, _, _ = ref.entry(row, col, ei, fj, N)
+        spent += time.perf_counter() - t0
+        out.append((idx, c_ij))
+    return out, spent
+
+
+def cpu_baseline(A_rm, B_rm, C_cm, N, mode, budget_s, seed=0, vectors=48):
+    """Time the CPU oracle computing sampled entries of the same product from
+    scratch (row and column norms, exponents, residues, N dot products, CRT,
+    unscaling) on the host's cores: one process per CPU this process may run
+    on (at most 16), each working through its own share of (row, column)
+    pairs of `vectors` seeded rows of A and columns of B for `budget_s`
+    seconds; every entry is checked bit for bit against the GPU."""
+    import multiprocessing as mp
+    import tempfile
+    import numpy as np
+    import torch
+
+    m, k = A_rm.shape
+    n = B_rm.shape[1]
+    rng = np.random.default_rng(seed)
+    ri = rng.choice(m, min(vectors, m), replace=False)
+    ci = rng.choice(n, min(vectors, n), replace=False)
+    cpu = host_cpu()
+    workers = max(1, min(16, cpu["cpus_allowed"] or 1))
+    pairs = [(len(ci) * a + b, (a, b)) for a in range(len(ri)) for b in range(len(ci))]
+    order = rng.permutation(len(pairs))
+    shares = [[pairs[int(x)] for x in order[w::workers]] for w in range(workers)]
+    with tempfile.TemporaryDirectory() as tmp:
+        rows_path, cols_path = os.path.join(tmp, "rows.npy"), os.path.join(tmp, "cols.npy")
+        rix = torch.as_tensor(ri, dtype=torch.long, device=A_rm.device)
+        cix = torch.as_tensor(ci, dtype=torch.long, device=B_rm.device)
+        np.save(rows_path, A_rm[rix].cpu().numpy())
+        np.save(cols_path, B_rm[:, cix].t().contiguous().cpu().numpy())
+        # fresh interpreters (spawn): the workers import numpy and the oracle only
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        pool = ctx.Pool(workers)
+        try:
+            res = pool.starmap_async(_oracle_entries, [
+                (rows_path, cols_path, sh, N, mode, budget_s) for sh in shares
+            ]).get(timeout=4 * budget_s + 120)
+        finally:
+            pool.terminate()
+            pool.join()
+        wall = time.perf_counter() - t0
+    done = exact_ok = 0
+    busy = 0.0
+    for out, spent in res:
+        busy += spent
+        for idx, c in out:
+            a, b = divmod(idx, len(ci))
+            g = float(C_cm[int(ci[b]), int(ri[a])])
+            exact_ok += int(np.float64(g).view(np.uint64) == np.float64(c).view(np.uint64))
+            done += 1
+    per_worker = busy / workers
+    return dict(value=2.0 * k * done / per_worker / 1e12, unit="TFLOPS", cores=workers,
+                kind="oracle",
+                sample=f"{done} entries C_ij of this workload, pairs of {len(ri)} seeded rows of A "
+                       f"and {len(ci)} seeded columns of B, each computed from scratch from its "
+                       f"full row and column (k={k}, N={N}) by {workers} worker processes: 2k "
+                       f"flops credited per entry, over the mean compute seconds per worker",
+                seconds=round(per_worker, 2), wall_seconds=round(wall, 2),
+                threads=f"{workers} processes x 1 thread (pure Python integers)",
+                **cpu), done, exact_ok
 
 
 def accurate_sample_check(A_rm, B_rm, C_cm, N, samples=8, seed=0):
@@ -424,6 +479,55 @@ def complex_leg(size, N, phi, seed, steps, warmup, samples=8):
                 max_rel_err_sampled=worst)
 
 
+def fp8_leg(size, N, phi, seed, steps, warmup):
+    """The FP8 (E4M3) engine variant (mode | OZ2_ENGINE_FP8) at m = n = k =
+    size beside the INT8 engine on the same operands: ms per call, 2mnk/t,
+    the engine rate of the residue products (four E4M3 products of 2mnk
+    flops per modulus) against the FP8 MFMA peak, and whether C is
+    bit-identical to the INT8 engine's."""
+    import torch
+    from paper_2606_29129_amd import inputs
+    from paper_2606_29129_amd import ozaki2 as oz
+
+    dev = torch.device("cuda:0")
+    A = inputs.ozaki_matrix_torch(size, size, phi, seed, 0, dev)
+    B = inputs.ozaki_matrix_torch(size, size, phi, seed, 1, dev)
+    A_cm, B_cm = A.t().contiguous(), B.t().contiguous()
+    del A, B
+    stream = torch.cuda.current_stream()
+    oz.ensure_workspace(oz.ozaki2_workspace_size(size, size, size, N, FP8_FLAG))
+    out = {}
+    Cs = {}
+    for name, mode in (("int8", 0), ("fp8", FP8_FLAG)):
+        C = torch.empty((size, size), dtype=torch.float64, device=dev)
+
+        def step():
+            rc = oz.ozaki2_dgemm(size, size, size, A_cm, size, B_cm, size, C, size, N, mode)
+            if rc:
+                raise oz.Ozaki2Error("ozaki2_dgemm", rc)
+
+        oz._check("ozaki2_set_timing", oz.ozaki2_set_timing(1))
+        per, _ = timed_steps(torch, step, stream, steps, warmup)
+        stage_ms, calls = oz.ozaki2_get_stage_times()
+        oz.ozaki2_set_timing(0)
+        ms = statistics.median(per)
+        k3 = stage_ms[2] / max(calls, 1)
+        engine_ops = (4.0 if mode else 1.0) * 2.0 * N * size ** 3
+        rate = engine_ops / (k3 * 1e-3) / 1e12
+        out[name] = dict(ms_per_call=round(ms, 4), tflops=round(2.0 * size ** 3 / (ms * 1e-3) / 1e12, 2),
+                         stage_ms={n: round(v / max(calls, 1), 4) for n, v in zip(oz.STAGE_NAMES, stage_ms)},
+                         products_rate=round(rate, 1),
+                         products_unit="TFLOP/s (E4M3)" if mode else "TOP/s (INT8)",
+                         products_frac=round(rate / (FP8_PEAK_TFLOPS if mode else INT8_PEAK_TOPS), 4))
+        Cs[name] = C
+    torch.cuda.synchronize()
+    same = torch.equal(Cs["int8"].view(torch.int64), Cs["fp8"].view(torch.int64))
+    del Cs, A_cm, B_cm
+    torch.cuda.empty_cache()
+    return dict(workload=f"square DGEMM m=n=k={size}, (rand-0.5)*exp({phi}*randn) seed {seed}, "
+                         f"revised scaling, N={N}", N=N, bit_identical_to_int8=bool(same), **out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +553,8 @@ def main():
     ap.add_argument("--no-error", action="store_true", help="skip the 512-entry error block")
     ap.add_argument("--no-complex", action="store_true", help="skip the ZGEMM leg")
     ap.add_argument("--complex-size", type=int, default=8192)
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 engine leg")
+    ap.add_argument("--fp8-size", type=int, default=8192)
     ap.add_argument("--traffic-calibration", type=int, default=0, metavar="BYTES",
                     help="before the steps, run one torch.abs over a float64 tensor of "
                          "BYTES bytes (the known-size kernel that scales rocprofv3 "
@@ -600,6 +706,13 @@ def main():
         _log(f"zgemm {args.complex_size}^3 N=14: {cplx['tflops']} TFLOPS (8mnk/t) vs native "
              f"{cplx['native_zgemm_tflops']}; INT8 GEMMs at {cplx['int8_gemm_top_s']} TOP/s")
 
+    fp8 = None
+    if not args.no_fp8:
+        fp8 = fp8_leg(args.fp8_size, 14, args.phi, args.seed, max(3, args.steps // 2), 2)
+        _log(f"fp8 engine {args.fp8_size}^3 N=14: {fp8['fp8']['tflops']} TFLOPS vs int8 "
+             f"{fp8['int8']['tflops']}; products {fp8['fp8']['products_rate']} TFLOP/s; "
+             f"bit-identical {fp8['bit_identical_to_int8']}")
+
     shape = f"m=n=k={m}" if m == n == k else f"m={m} n={n} k={k}"
     how_N = (f"N={N} from the autotuner for max rel. error {args.target:g}" if not args.N
              else f"N={N} (fixed)")
@@ -637,6 +750,7 @@ def main():
         "fixed_N14": n14,
         "batched": batched,
         "complex": cplx,
+        "fp8_engine": fp8,
         "context": {"paper_gh200_cublas_dgemm_tflops": 60.9,
                     "paper_gh200_ozaki2_dgemm_tflops_up_to": 80.2},
     }
