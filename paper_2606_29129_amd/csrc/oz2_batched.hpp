@@ -196,18 +196,30 @@ __global__ __launch_bounds__(256) void kb_gemm(const BatchProb* __restrict__ pro
   int i = blockIdx.x;
   if (i >= nitems) return;
   TileArgs cur = tile_args(probs, items, i);
+  int buf = 0;
+  bool loaded = false;
   for (;;) {
     const int inext = i + (int)gridDim.x;
     const bool more = inext < nitems;
     const TileArgs nxt = tile_args(probs, items, more ? inext : i);
+    // the next item's row panels (its first slab is loaded during this
+    // item's last slab)
+    const int8_t* nA =
+        more ? nxt.RA + ((int64_t)nxt.t * nxt.Mp + (int64_t)nxt.tm * kBatchTile) * nxt.Kp : nullptr;
+    const int8_t* nB =
+        more ? nxt.RB + ((int64_t)nxt.t * nxt.Np + (int64_t)nxt.tn * kBatchTile) * nxt.Kp : nullptr;
     // A 128 x 128 tile has only 4 MFMAs per k step per wave; two
     // workgroups share a CU (64 KiB of LDS each), hiding part of the
     // per-item latency of the small problems; barrier at the slab top.
-    gemm_tile<kBatchTile, kBatchTile, kBatchBK, 0, false, 2>(
+    // No barrier between items: the epilogue does not touch the LDS, and the
+    // next item's first barrier orders its loads after every wave's last
+    // reads of this item.
+    buf = gemm_tile<kBatchTile, kBatchTile, kBatchBK, 0, false, 2, 0, true>(
         cur.RA, cur.RB, (uint8_t*)cur.U, nullptr, nullptr, cur.m, cur.n, cur.Mp, cur.Np, cur.Kp,
-        (const ModTable*)cur.tab, cur.t, cur.tm, cur.tn, lds);
+        (const ModTable*)cur.tab, cur.t, cur.tm, cur.tn, lds, 0, -1, buf, loaded, nA, nB,
+        nxt.Kp);
     if (!more) break;
-    __syncthreads();  // every wave is done with the LDS before the next prologue
+    loaded = true;
     i = inext;
     cur = nxt;
   }

@@ -219,10 +219,11 @@ __global__ __launch_bounds__(256) void k2_split_contig_cplx(
 }
 
 // --- K4: both parts from the three planes ----------------------------------
-// U holds 3N planes (component c, modulus t at plane c N + t), each C mod p_t
-// in [0, p_t) in the GEMM's 32 x 32 block order.  For each entry and modulus:
-//   re = U0 - U1 (mod p),  im = U2 - U0 - U1 (mod p),  both in [0, p),
-// so the slice sums stay below 2^52 as in the real case.  One wave per
+// U holds 3N planes (component c, modulus t at plane c N + t), each
+// rmod(C, p_t) as a signed byte in the GEMM's 32 x 32 block order.  For each
+// entry and modulus re = U0 - U1 and im = U2 - U0 - U1, congruent to the two
+// parts modulo p_t and below 2^9 in magnitude, so the slice sums stay below
+// 2^53 (exact) as in the real case.  One wave per
 // 32 x 32 block; the lane's 16 accumulator-order entries in PASSES passes
 // (two accumulator sets, re and im).  Each entry is stored as one (re, im)
 // pair.
@@ -268,21 +269,17 @@ __global__ __launch_bounds__(256) void k4_crt_cplx(
           w[c][0] = *reinterpret_cast<const uint32_t*>(q);
         }
       }
-      const int p = (int)T.p[t];
       double wt[S];
 #pragma unroll
       for (int s = 0; s < S; ++s) wt[s] = T.w[t][s];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int sh = 8 * (r & 3);
-        const int u0 = (int)((w[0][r >> 2] >> sh) & 0xFFu);
-        const int u1 = (int)((w[1][r >> 2] >> sh) & 0xFFu);
-        const int u2 = (int)((w[2][r >> 2] >> sh) & 0xFFu);
-        int re = u0 - u1;
-        re += re < 0 ? p : 0;
-        int im = u2 - u0 - u1;
-        im += im < 0 ? p : 0;
-        im += im < 0 ? p : 0;
+        const int u0 = (int)(int8_t)(w[0][r >> 2] >> sh);
+        const int u1 = (int)(int8_t)(w[1][r >> 2] >> sh);
+        const int u2 = (int)(int8_t)(w[2][r >> 2] >> sh);
+        const int re = u0 - u1;
+        const int im = u2 - u0 - u1;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           ar[r][s] = fma(wt[s], (double)re, ar[r][s]);

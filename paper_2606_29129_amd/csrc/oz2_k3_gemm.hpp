@@ -12,7 +12,8 @@
 // global loads are in flight while the current one feeds the MFMAs.
 //
 // Epilogue: |C_t| <= k * 128^2 fits INT32 for k <= 2^17 (Section 2.2).  The
-// product is reduced to U_t = C_t mod p_t in [0, p_t) and stored as one byte
+// product is reduced to U_t = rmod(C_t, p_t) in [-(p_t-1)/2, (p_t-1)/2] (for
+// p_t = 256 the low byte, in [-128, 127]) and stored as one signed byte
 // per entry, in 32 x 32 blocks laid out in the MFMA accumulator order: block
 // (bi, bj) of plane t is 1024 contiguous bytes at ((t Nb + bj) Mb + bi) * 1024
 // (Mb = Mp/32, Nb = Np/32), lane l's 16 accumulators at byte 16 l.  K4 reads
@@ -22,7 +23,7 @@
 // not store the product at all: it folds it into row and column maxima with
 // integer atomicMax (entries are >= 0, and the maxima start at 0); 3 is EPI 0
 // for a later block of k (k > 2^17 is split into blocks whose INT32 products
-// are exact): U_t = (U_t + C_t mod p_t) mod p_t.
+// are exact): U_t = rmod(U_t + rmod(C_t, p_t), p_t).
 #pragma once
 
 #include <type_traits>
@@ -199,7 +200,7 @@ __device__ __forceinline__ void tile_epilogue(
           } else {
             double y = (double)c;
             double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
-            u = (uint32_t)(int)(r < 0.0 ? r + p : r);
+            u = (uint32_t)(int)r & 0xFFu;         // its two's-complement byte
           }
           b |= u << (8 * e);
         }
@@ -209,18 +210,19 @@ __device__ __forceinline__ void tile_epilogue(
       const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;
       uint8_t* dst = U + (((int64_t)t * Nb + bj) * Mb + bi) * 1024 + lane * 16;
       if constexpr (EPI == 3) {
-        // a later k block: U = (U + C mod p) mod p, byte by byte
+        // a later k block: U = rmod(U + rmod(C, p), p), byte by byte (the
+        // low byte of the sum for p = 256)
         const uint4 o = *reinterpret_cast<const uint4*>(dst);
         const uint32_t ow[4] = {o.x, o.y, o.z, o.w};
-        const uint32_t pu = (uint32_t)p;
+        const int pi = (int)p, half = (int)p >> 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           uint32_t b = 0;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            uint32_t v = ((ow[q] >> (8 * e)) & 0xFFu) + ((w[q] >> (8 * e)) & 0xFFu);
-            v = is256 ? (v & 0xFFu) : (v >= pu ? v - pu : v);
-            b |= v << (8 * e);
+            int v = (int)(int8_t)(ow[q] >> (8 * e)) + (int)(int8_t)(w[q] >> (8 * e));
+            if (!is256) v = v > half ? v - pi : (v < -half ? v + pi : v);
+            b |= ((uint32_t)v & 0xFFu) << (8 * e);
           }
           w[q] = b;
         }
@@ -258,14 +260,25 @@ __device__ __forceinline__ void tile_epilogue(
 // last slabs are separate copies of the body without the loads (and reads
 // ahead) that have no slab to target, so that every slab body is one basic
 // block without conditional loads.
+//
+// PF (persistent callers, barrier at the slab top only): the tile starts in
+// LDS buffer buf0, its first slab already loaded there if `loaded`; during
+// its last slab it issues the first slab of the caller's next tile (nA, nB:
+// that tile's row panels of A and B; nKp its row length; null: no next tile)
+// into the other buffer, which no wave reads any more once all have passed
+// the last slab's barrier, so those loads fly during the last MFMAs and the
+// epilogue.  Returns the buffer holding the next tile's first slab.
 template <int BM, int BN, int BK, int EPI, bool EARLY_BARRIER = (BM >= 256 && BN >= 256),
-          int LSTEPS = (EARLY_BARRIER ? 2 : 3), int LX = (EARLY_BARRIER ? 8 : 0)>
-__device__ __forceinline__ void gemm_tile(
+          int LSTEPS = (EARLY_BARRIER ? 2 : 3), int LX = (EARLY_BARRIER ? 8 : 0), bool PF = false>
+__device__ __forceinline__ int gemm_tile(
     const int8_t* __restrict__ RA, const int8_t* __restrict__ RB,
     uint8_t* __restrict__ U, int32_t* __restrict__ aux0, int32_t* __restrict__ aux1,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, int64_t Kp,
     const ModTable* __restrict__ tab, int t, int tm, int tn,
-    int8_t (*__restrict__ lds)[(BM + BN) * BK], int64_t k0 = 0, int64_t klen = -1) {
+    int8_t (*__restrict__ lds)[(BM + BN) * BK], int64_t k0 = 0, int64_t klen = -1,
+    int buf0 = 0, bool loaded = false, const int8_t* nA = nullptr, const int8_t* nB = nullptr,
+    int64_t nKp = 0) {
+  static_assert(!PF || !EARLY_BARRIER, "prefetch across tiles needs the slab-top barrier");
   constexpr int TM = BM / 64, TN = BN / 64;      // 32x32 blocks per wave
   constexpr int CH = BK / 16;                    // 16-byte chunks per row
   constexpr int A_LOADS = BM * CH / 256, B_LOADS = BN * CH / 256;
@@ -307,6 +320,19 @@ __device__ __forceinline__ void gemm_tile(
                  lds[buf] + BM * BK + ((i - A_LOADS) * 256 + wave * 64) * 16);
   };
 
+  // Load round i of the caller's next tile's first slab into buffer buf.
+  auto gload_next1 = [&](int buf, int i) {
+    if (i < A_LOADS) {
+      const int s = i * 256 + tid, row = s / CH;
+      load_lds16(nA + (int64_t)row * nKp + swz_chunk<BK>(row, s % CH) * 16,
+                 lds[buf] + (i * 256 + wave * 64) * 16);
+    } else {
+      const int s = (i - A_LOADS) * 256 + tid, row = s / CH;
+      load_lds16(nB + (int64_t)row * nKp + swz_chunk<BK>(row, s % CH) * 16,
+                 lds[buf] + BM * BK + ((i - A_LOADS) * 256 + wave * 64) * 16);
+    }
+  };
+
   // Fragment q (TM blocks of A, then TN blocks of B) of k step kk of LDS
   // buffer buf into register set F.
   v4i fa[2][TM], fb[2][TN];
@@ -344,8 +370,10 @@ __device__ __forceinline__ void gemm_tile(
   static_assert(LX == 0 || (EARLY_BARRIER && LX <= NM - BAR - 1 && LX <= 63), "early loads");
 
   const int nk = (int)(klen / BK);
+  if (!PF || !loaded) {
 #pragma unroll
-  for (int i = 0; i < LOADS; ++i) gload1(0, 0, i);
+    for (int i = 0; i < LOADS; ++i) gload1(PF ? buf0 : 0, 0, i);
+  }
   if constexpr (EARLY_BARRIER) {
     if (LX > 0 && nk > 1) {
 #pragma unroll
@@ -360,11 +388,13 @@ __device__ __forceinline__ void gemm_tile(
   }
   // One slab.  MORE: a next slab exists (load the rest of it, meet at the
   // barrier, read ahead); MORE2: a slab after that exists (its first LX
-  // loads).  Separate copies, so that each stays one basic block.
-  int buf = 0;
-  auto slab = [&](int kt, auto more_tag, auto more2_tag) {
+  // loads); NEXT (last slab, PF): load the next tile's first slab.
+  // Separate copies, so that each stays one basic block.
+  int buf = PF ? buf0 : 0;
+  auto slab = [&](int kt, auto more_tag, auto more2_tag, auto next_tag) {
     constexpr bool MORE = decltype(more_tag)::value;
     constexpr bool MORE2 = decltype(more2_tag)::value;
+    constexpr bool NEXT = decltype(next_tag)::value;
     const int64_t knext = (int64_t)(kt + 1) * BK;
     if constexpr (!EARLY_BARRIER) {
       // Barrier at the top of the slab: slab kt is in LDS and every wave is
@@ -398,6 +428,10 @@ __device__ __forceinline__ void gemm_tile(
           const int g = LX + kk * PER + idx / SP;
           if (g < LOADS) gload1(buf ^ 1, knext, g);
         }
+        if (NEXT && kk < LSTEPS && PER > 0 && idx % SP == SP - 1) {
+          const int g = kk * PER + idx / SP;
+          if (g < LOADS) gload_next1(buf ^ 1, g);
+        }
         if (MORE && EARLY_BARRIER && kk == KS - 1 && idx >= BAR && idx < BAR + NF)
           fread1(buf ^ 1, 0, 0, idx - BAR);
         if (MORE2 && LX > 0 && kk == KS - 1 && idx > BAR && idx <= BAR + LX)
@@ -408,12 +442,17 @@ __device__ __forceinline__ void gemm_tile(
     buf ^= 1;
   };
   int kt = 0;
-  for (; kt + 2 < nk; ++kt) slab(kt, std::true_type{}, std::true_type{});
-  if (nk >= 2) slab(nk - 2, std::true_type{}, std::false_type{});
-  slab(nk - 1, std::false_type{}, std::false_type{});
-  wait_vmem_all();  // no load may still target LDS when the tile returns
+  for (; kt + 2 < nk; ++kt) slab(kt, std::true_type{}, std::true_type{}, std::false_type{});
+  if (nk >= 2) slab(nk - 2, std::true_type{}, std::false_type{}, std::false_type{});
+  if (PF && nA) {
+    slab(nk - 1, std::false_type{}, std::false_type{}, std::bool_constant<PF>{});
+  } else {
+    slab(nk - 1, std::false_type{}, std::false_type{}, std::false_type{});
+    wait_vmem_all();  // no load may still target LDS when the tile returns
+  }
 
   tile_epilogue<BM, BN, EPI>(acc, U, aux0, aux1, m, n, Mp, Np, tab, t, tm, tn, wm, wn, lane);
+  return buf;
 }
 
 template <int BM, int BN, int BK, int EPI>

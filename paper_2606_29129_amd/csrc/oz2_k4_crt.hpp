@@ -1,14 +1,15 @@
 // oz2_k4_crt.hpp -- K4: CRT reconstruction (Step 3) and unscaling (Step 4).
 //
-// For each output entry, with U_t = C_t mod p_t from K3:
+// For each output entry, with U_t = rmod(C_t, p_t) from K3 (a signed byte;
+// any representative of C_t modulo p_t of magnitude < 2^9 would do):
 //   X   = sum_t W_t U_t,   W_t = P_t q_t  (< P)           (eq. os2-C')
 //   C'' = X - P round(X / P)  in (-P/2, P/2)                (eq. os2-C'')
 //   C   = RN(C'' 2^-(e_i + f_j))                            (Step 4)
 // Because |A'B'| < P/2 (eq. os2-condition), C'' = A'B' exactly.
 //
 // Exact arithmetic in binary64: W_t is held as 39-bit slices w_ts, so each
-// slice sum Acc_s = sum_t w_ts U_t < 20 * 2^39 * 255 < 2^52 is exact.  The
-// quotient Q = round(X / P) (< 2^13) is estimated from a rounded X; every
+// slice sum |Acc_s| = |sum_t w_ts U_t| < 20 * 2^39 * 2^9 < 2^53 is exact.
+// The quotient Q = round(X / P) (|Q| < 2^14) is estimated from a rounded X; every
 // R_s = Acc_s - Q P_s is exact, carries are propagated exactly, and an exact
 // signed comparison with P/2 corrects a quotient that is off by one (skipped
 // when a rounded value of R already shows |R| < P/4).  The
@@ -175,7 +176,7 @@ __device__ __forceinline__ void k4_crt_body(
       for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double u = (double)((ws[r >> 2] >> (8 * (r & 3))) & 0xFFu);
+        const double u = (double)(int)(int8_t)(ws[r >> 2] >> (8 * (r & 3)));
 #pragma unroll
         for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
       }

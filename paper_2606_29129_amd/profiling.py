@@ -4,6 +4,7 @@
     python -m paper_2606_29129_amd.profiling traffic FETCH_DIR WRITE_DIR COMMAND \
         --workload "m=16384 n=16384 k=16384 N=14" --copy-bytes B > traffic.txt
     python -m paper_2606_29129_amd.profiling counters COMMAND DIR... --ms T --ops X
+    python -m paper_2606_29129_amd.profiling batch [--replays R] [--timing]
 
 ``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
 --stats --output-format csv`` writes and prints a short markdown table of the
@@ -210,6 +211,61 @@ def counters_markdown(dirs, cmd: str, kernel: str, ms_per_launch: float, ops_per
     return "\n".join(out) + "\n"
 
 
+def batch_problems(count=256, seed=0):
+    """The batch of the benchmark's batched leg: m, n, k each
+    round(exp(U(ln 64, ln 2048))), phi ~ U(0.5, 3), problem i from seed + i.
+    Returns [(m, n, k, phi, seed_i)]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    shapes = np.exp(rng.uniform(np.log(64), np.log(2048), (count, 3))).round().astype(int)
+    phis = rng.uniform(0.5, 3.0, count)
+    return [(int(m), int(n), int(k), float(phis[i]), seed + i)
+            for i, (m, n, k) in enumerate(shapes)]
+
+
+def run_batch(replays=3, count=256, seed=0, target=1e-15, timing=False):
+    """Driver for profiling the batched path: the benchmark's batch with its
+    operands generated on the host (numpy) and copied to the GPU, so that the
+    only kernels of the process are the library's own (profilers then see no
+    framework kernels); one call with N = 0 (the library's autotuner for the
+    target), then `replays` graph replays with the chosen N.  Prints the
+    median replay time."""
+    import statistics
+    import time
+    import torch
+    from paper_2606_29129_amd import inputs
+    from paper_2606_29129_amd import ozaki2 as oz
+    dev = torch.device("cuda:0")
+    pairs = []
+    for m, n, k, phi, s in batch_problems(count, seed):
+        A = torch.from_numpy(inputs.ozaki_matrix(m, k, phi, s, 0)).to(dev)
+        B = torch.from_numpy(inputs.ozaki_matrix(k, n, phi, s, 1)).to(dev)
+        pairs.append((A, B))
+    outs, Ns = oz.dgemm_batched(pairs, 0, target=target, return_N=True)
+    probs = [(B.shape[1], A.shape[0], A.shape[1], B, max(1, B.shape[1]), A, max(1, A.shape[1]),
+              C, max(1, B.shape[1]), N) for (A, B), C, N in zip(pairs, outs, Ns)]
+    oz.ensure_workspace(oz.ozaki2_dgemm_batched_workspace_size(probs))
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    if timing:
+        oz.ozaki2_set_timing(1)
+    per = []
+    for _ in range(replays):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, bad, _ = oz.ozaki2_dgemm_batched(probs, 0)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) * 1e3)
+        if rc:
+            raise oz.Ozaki2Error(f"ozaki2_dgemm_batched (problem {bad})", rc)
+    print(f"batch of {count}: N {min(Ns)}..{max(Ns)}, median replay {statistics.median(per):.3f} ms "
+          f"(host clock)", flush=True)
+    if timing:
+        st, calls = oz.ozaki2_get_stage_times()
+        oz.ozaki2_set_timing(0)
+        print("stages ms/call:", {n: round(v / max(calls, 1), 4)
+                                  for n, v in zip(oz.STAGE_NAMES, st)}, flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -229,8 +285,14 @@ def main(argv=None):
     c.add_argument("--kernel", default=K3_NAME)
     c.add_argument("--ms", type=float, required=True, help="average launch time, ms")
     c.add_argument("--ops", type=float, required=True, help="algorithmic ops per launch")
+    b = sub.add_parser("batch", help="run the benchmark's batch (host-generated operands)")
+    b.add_argument("--replays", type=int, default=3)
+    b.add_argument("--count", type=int, default=256)
+    b.add_argument("--timing", action="store_true", help="stage events instead of the graph")
     a = ap.parse_args(argv)
-    if a.what == "counters":
+    if a.what == "batch":
+        run_batch(a.replays, a.count, timing=a.timing)
+    elif a.what == "counters":
         sys.stdout.write(counters_markdown(a.dirs, a.command, a.kernel, a.ms, a.ops))
     elif a.what == "stats":
         sys.stdout.write(stats_markdown(a.dir, a.title, a.command))
