@@ -208,3 +208,28 @@ def test_batched_autotune_picks_the_python_N_and_same_bits():
     f = torch.zeros((5, 3), dtype=torch.float64, device=DEV)
     _, used2 = oz.dgemm_batched(pairs[:3] + [(e, f)], [7, 0, 0, 0], target=1e-15, return_N=True)
     assert used2 == [7, want[1], want[2], 0]
+
+
+def test_batched_original_fast_mode_equals_single_calls_and_oracle():
+    """Mode 1 (Algorithm 1, Section 2.3) through the batched path -- its own
+    route through the row and column maxima and the Algorithm 1 fold --
+    on uneven shapes: every problem bit-identical to one ozaki2_dgemm call
+    in mode 1, and the small problems to the oracle."""
+    probs = _problems(6, 14)
+    pairs = [(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)) for A, B, _ in probs]
+    Ns = [N for _, _, N in probs]
+    print(f"original mode batch: shapes {[a.shape + (b.shape[1],) for a, b, _ in probs][:6]} ...",
+          flush=True)
+    for rep in range(2):   # the second call replays the graph
+        outs = oz.dgemm_batched(pairs, Ns, mode="original")
+        torch.cuda.synchronize()
+        for (Ad, Bd), N, C in zip(pairs, Ns, outs):
+            single = oz.dgemm(Ad, Bd, N=N, mode="original").cpu().numpy()
+            assert np.array_equal(_bits(C.cpu().numpy()), _bits(single))
+    for (A, B, N), C in list(zip(probs, outs))[:5]:
+        assert np.array_equal(_bits(C.cpu().numpy()), _bits(ref.dgemm(A, B, N, ref.ORIGINAL)))
+    # the two modes differ on these inputs (Algorithm 1 is not Algorithm 2)
+    rev = oz.dgemm_batched(pairs, Ns)
+    torch.cuda.synchronize()
+    assert any(not np.array_equal(_bits(a.cpu().numpy()), _bits(b.cpu().numpy()))
+               for a, b in zip(rev, outs))
