@@ -275,6 +275,38 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 
 // Status word reset at the start of each call (a kernel, not a memset, so
 // the call can be captured in a graph).
+// Both operands in one launch (the two halves are independent, so at small
+// sizes they overlap instead of running one after the other): blocks
+// [0, nA) take the rows of A (nA = gAx x ceil(nchunks / 4) blocks of the
+// strided kernel's grid), the others the columns of B.  Block 0 also clears
+// the status word, which only later launches read or write.
+template <typename T>
+__global__ __launch_bounds__(256) void k1_partials_ab(
+    const T* __restrict__ A, int64_t lda, int64_t m, const T* __restrict__ B, int64_t ldb,
+    int64_t n, int64_t k, int64_t nchunks, double* __restrict__ partA,
+    double* __restrict__ maxA, double* __restrict__ partB, double* __restrict__ maxB,
+    int64_t gAx, int64_t nA, int* __restrict__ status) {
+  const int64_t b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) status[0] = 0;
+  if (b < nA)
+    k1_partials_strided_body<T>(A, lda, m, k, nchunks, partA, maxA, b % gAx, b / gAx);
+  else
+    k1_partials_contig_body<T>(B, ldb, n, k, nchunks, partB, maxB, b - nA);
+}
+
+// Both folds in one launch: blocks [0, nA) for the rows of A, the rest for
+// the columns of B.
+__global__ __launch_bounds__(256) void k1_fold_ab(
+    const double* __restrict__ partA, const double* __restrict__ maxA, int64_t m,
+    int32_t* __restrict__ eA, double* __restrict__ SA, const double* __restrict__ partB,
+    const double* __restrict__ maxB, int64_t n, int32_t* __restrict__ eB,
+    double* __restrict__ SB, int64_t nchunks, int mode, const ModTable* __restrict__ tab,
+    int* __restrict__ status, int64_t nA) {
+  const int64_t b = blockIdx.x;
+  if (b < nA) k1_fold_body(partA, maxA, nchunks, m, mode, tab, eA, SA, status, b);
+  else k1_fold_body(partB, maxB, nchunks, n, mode, tab, eB, SB, status, b - nA);
+}
+
 __global__ void k_clear_status(int* status) {
   if (threadIdx.x == 0) status[0] = 0;
 }

@@ -216,6 +216,22 @@ __global__ __launch_bounds__(256) void k2_split_contig(
   k2_split_contig_body<T, LIMBS>(X, ld, nvec, k, e, tab, N, R, Vp, Kp, blockIdx.x);
 }
 
+// Both operands in one launch: blocks [0, nA) run the strided kernel's
+// blocks for A (nA = gAx x Kp / kK2HB, gAx = Mp / kK2VB), the others the
+// contiguous kernel's blocks for B.
+template <typename T, int LIMBS>
+__global__ __launch_bounds__(256) void k2_split_ab(
+    const T* __restrict__ A, int64_t lda, int64_t m, const int32_t* __restrict__ eA,
+    int8_t* __restrict__ RA, int64_t Mp, const T* __restrict__ B, int64_t ldb, int64_t n,
+    const int32_t* __restrict__ eB, int8_t* __restrict__ RB, int64_t Np, int64_t k,
+    const ModTable* __restrict__ tab, int N, int64_t Kp, int64_t gAx, int64_t nA) {
+  const int64_t b = blockIdx.x;
+  if (b < nA)
+    k2_split_strided_body<T, LIMBS>(A, lda, m, k, eA, tab, N, RA, Mp, Kp, b % gAx, b / gAx);
+  else
+    k2_split_contig_body<T, LIMBS>(B, ldb, n, k, eB, tab, N, RB, Np, Kp, b - nA);
+}
+
 // Accurate mode: abar = ceil(|a| 2^e') in [0, 64] (Section 2.3), one int8
 // plane in the GEMM layout.  Vectors with exponent kExpZero or
 // kExpNonFinite give zeros.

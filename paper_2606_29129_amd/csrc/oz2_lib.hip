@@ -287,12 +287,11 @@ struct Debug {
 template <typename T, int LIMBS>
 void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, int64_t n,
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
-  dim3 gA((unsigned)(L.Mp / kK2VB), (unsigned)(L.Kp / kK2HB));
-  k2_split_strided<T, LIMBS><<<gA, 256, 0, g_stream>>>(
-      A, lda, m, k, (const int32_t*)(ws + L.eA), tab, N, (int8_t*)(ws + L.RA), L.Mp, L.Kp);
-  int64_t work = L.Np * (L.Kp / kK2EPT);
-  k2_split_contig<T, LIMBS><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
-      B, ldb, n, k, (const int32_t*)(ws + L.eB), tab, N, (int8_t*)(ws + L.RB), L.Np, L.Kp);
+  const int64_t gAx = L.Mp / kK2VB, nA = gAx * (L.Kp / kK2HB);
+  const int64_t nB = (L.Np * (L.Kp / kK2EPT) + 255) / 256;
+  k2_split_ab<T, LIMBS><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
+      A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
+      (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA);
 }
 
 // K3 over the planes given by (t, planes): EPI 0 runs all N planes (t
@@ -389,23 +388,24 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
   StageClock clk(!fixed_ws);
   clk.mark(0);
   // K1: squared norms and exponents.
-  k_clear_status<<<1, 64, 0, g_stream>>>((int*)(ws + L.status));
   {
     double* pmA = L.maxA ? (double*)(ws + L.maxA) : nullptr;
     double* pmB = L.maxB ? (double*)(ws + L.maxB) : nullptr;
     dim3 gA((unsigned)((m + 63) / 64), (unsigned)((L.nch + 3) / 4));
-    k1_partials_strided<T><<<gA, 256, 0, g_stream>>>(A, lda, m, k, L.nch,
-                                                     (double*)(ws + L.partA), pmA);
     int64_t work = n * L.nch;
-    k1_partials_contig<T><<<(unsigned)((work + 255) / 256), 256, 0, g_stream>>>(
-        B, ldb, n, k, L.nch, (double*)(ws + L.partB), pmB);
+    {
+      // both operands' partial sums (and the status word's reset) in one launch
+      const int64_t nA = (int64_t)gA.x * gA.y, nB = (work + 255) / 256;
+      k1_partials_ab<T><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
+          A, lda, m, B, ldb, n, k, L.nch, (double*)(ws + L.partA), pmA, (double*)(ws + L.partB),
+          pmB, (int64_t)gA.x, nA, (int*)(ws + L.status));
+    }
     if (mode != OZ2_MODE_ACCURATE) {
-      k1_fold<<<(unsigned)((m + 255) / 256), 256, 0, g_stream>>>(
-          (double*)(ws + L.partA), pmA, L.nch, m, mode, tab, (int32_t*)(ws + L.eA),
-          (double*)(ws + L.SA), (int*)(ws + L.status));
-      k1_fold<<<(unsigned)((n + 255) / 256), 256, 0, g_stream>>>(
-          (double*)(ws + L.partB), pmB, L.nch, n, mode, tab, (int32_t*)(ws + L.eB),
-          (double*)(ws + L.SB), (int*)(ws + L.status));
+      const int64_t fA = (m + 255) / 256, fB = (n + 255) / 256;
+      k1_fold_ab<<<(unsigned)(fA + fB), 256, 0, g_stream>>>(
+          (double*)(ws + L.partA), pmA, m, (int32_t*)(ws + L.eA), (double*)(ws + L.SA),
+          (double*)(ws + L.partB), pmB, n, (int32_t*)(ws + L.eB), (double*)(ws + L.SB), L.nch,
+          mode, tab, (int*)(ws + L.status), fA);
       if (mode == OZ2_MODE_EXACT) {
         // Fallback for the vectors whose squared norm overflowed: the partial
         // sums again over the scaled-down entries (other vectors exit at
