@@ -124,111 +124,108 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
   return neg ? -res : res;
 }
 
-// One wave per 32 x 32 block; lane l owns the 16 entries of the MFMA
-// accumulator layout (acc_row, acc_col).  The results go through a per-wave
-// LDS tile (column-major, columns padded to 33 entries) so that each store
-// instruction writes two whole 32-entry column segments of C.
+// Two waves per 32 x 32 block: wave h (0 or 1) of the block takes the 8
+// accumulator-order entries 8h .. 8h + 7 of each lane, i.e. rows 16h ..
+// 16h + 15 of the block (all 32 columns), 8 of the 16 bytes each plane holds
+// per lane.  (Twice the waves of one wave per block: at small sizes the grid
+// is otherwise a single wave per SIMD whose plane loads and reconstruction
+// run back to back.)  The results go through a per-wave LDS tile so that
+// each store instruction writes four 16-entry column segments of C.
+constexpr int kK4WavesPerBlock = 2;
+
 template <int S, typename TO>
 __device__ __forceinline__ void k4_crt_body(
     const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
     const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc, int64_t bx) {
-  __shared__ TO tile[4][32][33];
+  __shared__ TO tile[4][16][33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t Mb = Mp / 32, Nb = Np / 32;
-  const int64_t blk = bx * 4 + wave;
+  const int64_t wid = bx * 4 + wave;
+  const int64_t blk = wid / kK4WavesPerBlock;
+  const int h = (int)(wid % kK4WavesPerBlock);
   const int64_t mb_used = (m + 31) / 32;
   const int64_t nb_used = (n + 31) / 32;
   if (blk >= mb_used * nb_used) return;  // whole wave: the tile is per wave
   const int64_t bi = blk % mb_used, bj = blk / mb_used;
-  const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16;
+  const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16 + 8 * h;
   const int64_t plane = Nb * Mb * 1024;
   const int lc = acc_col(lane);
   const int64_t col = bj * 32 + lc;
   const int32_t f = col < n ? eB[col] : 0;
   const ModTable& T = *tab;
-  // With 4 slices, two passes over the planes, each for 8 of the lane's 16
-  // entries (8 of its 16 bytes per plane): half the accumulator registers
-  // (occupancy), no extra reads.  With fewer slices one pass.
   // The plane bytes are loaded in groups of PF planes, the next group's
   // loads issued before the current group is accumulated, so a wave waits
   // for memory once per group instead of once per plane.
-  constexpr int PASSES = S >= 4 ? 2 : 1, R = 16 / PASSES, RW = R / 4, PF = 4;
+  constexpr int R = 8, RW = 2, PF = 4;
+  double acc[R][S];
 #pragma unroll
-  for (int h = 0; h < PASSES; ++h) {
-    double acc[R][S];
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
+  auto load_plane = [&](int t, uint32_t (&ws)[RW]) {
+    const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane);
+    ws[0] = w.x;
+    ws[1] = w.y;
+  };
+  auto accumulate = [&](int t, const uint32_t (&ws)[RW]) {
+    double wt[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
-    auto load_plane = [&](int t, uint32_t (&ws)[RW]) {
-      if constexpr (R == 16) {
-        const uint4 w = *reinterpret_cast<const uint4*>(src + (int64_t)t * plane);
-        ws[0] = w.x; ws[1] = w.y; ws[2] = w.z; ws[3] = w.w;
-      } else {
-        const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane + 8 * h);
-        ws[0] = w.x; ws[1] = w.y;
-      }
-    };
-    auto accumulate = [&](int t, const uint32_t (&ws)[RW]) {
-      double wt[S];
-#pragma unroll
-      for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double u = (double)(int)(int8_t)(ws[r >> 2] >> (8 * (r & 3)));
-#pragma unroll
-        for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
-      }
-    };
-    uint32_t cur[PF][RW] = {}, nxt[PF][RW] = {};
-#pragma unroll
-    for (int i = 0; i < PF; ++i)
-      if (i < N) load_plane(i, cur[i]);
-    for (int t0 = 0; t0 < N; t0 += PF) {
-#pragma unroll
-      for (int i = 0; i < PF; ++i)
-        if (t0 + PF + i < N) load_plane(t0 + PF + i, nxt[i]);
-#pragma unroll
-      for (int i = 0; i < PF; ++i)
-        if (t0 + i < N) accumulate(t0 + i, cur[i]);
-#pragma unroll
-      for (int i = 0; i < PF; ++i)
-#pragma unroll
-        for (int q = 0; q < RW; ++q) cur[i][q] = nxt[i][q];
-    }
+    for (int s = 0; s < S; ++s) wt[s] = tab->w[t][s];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int lr = acc_row(R * h + r, lane);
-      const int64_t row = bi * 32 + lr;
-      double v = 0.0;
-      if (row < m && col < n) {
-        const int32_t e = eA[row];
-        if (e == kExpNonFinite || f == kExpNonFinite) {
-          v = __builtin_nan("");
-        } else {
-          double a[S];
+      const double u = (double)(int)(int8_t)(ws[r >> 2] >> (8 * (r & 3)));
 #pragma unroll
-          for (int s = 0; s < S; ++s) a[s] = acc[r][s];
-          if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
-          else v = crt_unscale<S, 24, -149>(a, T, e + f);
-        }
-      }
-      tile[wave][lc][lr] = (TO)v;
+      for (int s = 0; s < S; ++s) acc[r][s] = fma(wt[s], u, acc[r][s]);
     }
+  };
+  uint32_t cur[PF][RW] = {}, nxt[PF][RW] = {};
+#pragma unroll
+  for (int i = 0; i < PF; ++i)
+    if (i < N) load_plane(i, cur[i]);
+  for (int t0 = 0; t0 < N; t0 += PF) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+      if (t0 + PF + i < N) load_plane(t0 + PF + i, nxt[i]);
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+      if (t0 + i < N) accumulate(t0 + i, cur[i]);
+#pragma unroll
+    for (int i = 0; i < PF; ++i)
+#pragma unroll
+      for (int q = 0; q < RW; ++q) cur[i][q] = nxt[i][q];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = acc_row(R * h + r, lane);     // 16 h .. 16 h + 15
+    const int64_t row = bi * 32 + lr;
+    double v = 0.0;
+    if (row < m && col < n) {
+      const int32_t e = eA[row];
+      if (e == kExpNonFinite || f == kExpNonFinite) {
+        v = __builtin_nan("");
+      } else {
+        double a[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) a[s] = acc[r][s];
+        if constexpr (sizeof(TO) == 8) v = crt_unscale<S, 53, -1074>(a, T, e + f);
+        else v = crt_unscale<S, 24, -149>(a, T, e + f);
+      }
+    }
+    tile[wave][lr - 16 * h][lc] = (TO)v;
   }
   // LDS operations of one wave complete in order; the fence keeps the
   // compiler from moving the reads above the writes.
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int orow = lane & 31;
-  const int64_t row = bi * 32 + orow;
+  const int orow = lane & 15;
+  const int64_t row = bi * 32 + 16 * h + orow;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int oc = 2 * i + (lane >> 5);
+  for (int i = 0; i < 8; ++i) {
+    const int oc = 4 * i + (lane >> 4);
     const int64_t c = bj * 32 + oc;
-    if (row < m && c < n) C[row + c * ldc] = tile[wave][oc][orow];
+    if (row < m && c < n) C[row + c * ldc] = tile[wave][orow][oc];
   }
 }
 

@@ -333,8 +333,8 @@ void launch_gemm_blocked(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* U
 template <int S, typename TO>
 void launch_crt(const Layout& L, char* ws, const ModTable* tab, int N, int64_t m, int64_t n,
                 TO* C, int64_t ldc) {
-  int64_t blocks = ((m + 31) / 32) * ((n + 31) / 32);
-  k4_crt<S, TO><<<(unsigned)((blocks + 3) / 4), 256, 0, g_stream>>>(
+  int64_t waves = ((m + 31) / 32) * ((n + 31) / 32) * kK4WavesPerBlock;
+  k4_crt<S, TO><<<(unsigned)((waves + 3) / 4), 256, 0, g_stream>>>(
       (const uint8_t*)(ws + L.U), (const int32_t*)(ws + L.eA), (const int32_t*)(ws + L.eB),
       tab, N, m, n, L.Mp, L.Np, C, ldc);
 }
@@ -812,7 +812,7 @@ int plan_batch(int batch, const oz2_problem* P, int mode, size_t tune_ops, Batch
         case kB_FOLDB: c = (q.n + 255) / 256; break;
         case kB_K2A: c = (L.Mp / kK2VB) * (L.Kp / kK2HB); break;
         case kB_K2B: c = (L.Np * (L.Kp / kK2EPT) + 255) / 256; break;
-        default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) + 3) / 4; break;
+        default: c = (((q.m + 31) / 32) * ((q.n + 31) / 32) * kK4WavesPerBlock + 3) / 4; break;
       }
       pl->prefix[(size_t)st * (na + 1) + a] = acc;
       acc += c;
