@@ -91,17 +91,17 @@ int g_tile_policy = OZ2_TILE_AUTO;
 // Automatic tile choice: a cost model over the padded work and the number of
 // workgroup rounds.  A 256 x 256 tile runs one workgroup per CU, the smaller
 // tiles two.  Per CU and unit of padded output the smaller tiles are slower
-// (128 x 128 at 0.80, 256 x 64 at 0.50 of the 256 x 256 rate), but with two
+// (128 x 128 at 0.75, 256 x 64 at 0.45 of the 256 x 256 rate), but with two
 // workgroups per CU one's prologue and epilogue overlap the other's main
-// loop, while a 256 x 256 round pays them in full (counted as 4 k slabs).
+// loop, while a 256 x 256 round pays them in full (counted as 2 k slabs).
 // The constants are the fit (autotune.fit_tile_model) to measured times of
 // the three tiles (autotune_tiles.json) on 13 shapes
 // (square 512..16384, k from 512 to 16384, n = 64..256 skinny) at N = 14
-// and 20: the model's pick is never more than 0.5% slower than the best.
+// and 20: the model's pick is never more than 0.6% slower than the best.
 int choose_tile(int64_t m, int64_t n, int64_t k, int N) {
-  constexpr double kRate[4] = {0.0, 1.0, 0.80, 0.50};
+  constexpr double kRate[4] = {0.0, 1.0, 0.75, 0.45};
   constexpr int kPerCU[4] = {0, 1, 2, 2};
-  constexpr double kFixed[4] = {0.0, 4.0, 0.0, 0.0};
+  constexpr double kFixed[4] = {0.0, 2.0, 0.0, 0.0};
   const double slabs = (double)((k + kBK - 1) / kBK);
   int best = OZ2_TILE_256x256;
   double best_t = 0.0;

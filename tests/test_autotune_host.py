@@ -59,7 +59,7 @@ def test_library_tile_choice_matches_measurements():
             pick = oz.ozaki2_get_tile(rec["m"], rec["n"], rec["k"], N)
             assert ms[pick] <= 1.02 * min(ms.values()), (rec["m"], rec["n"], rec["k"], N, pick)
     rate, fixed, tot, worst = autotune.fit_tile_model(table)
-    assert rate == {1: 1.0, 2: 0.8, 3: 0.5} and fixed == {1: 4, 2: 0, 3: 0}
+    assert rate == {1: 1.0, 2: 0.75, 3: 0.45} and fixed == {1: 2, 2: 0, 3: 0}
     assert worst < 0.01
 
 
