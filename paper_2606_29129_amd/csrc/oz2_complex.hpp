@@ -108,19 +108,19 @@ __device__ __forceinline__ void pack_cplx(const Limbs<LIMBS> (&Lr)[EPL],
                                           const ModTable* __restrict__ tab, uint2 (&w)[3]) {
   static_assert(EPL == 8, "two dwords per component");
   const int p = (int)tab->p[t];
-  uint32_t b[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  uint32_t v[3][EPL];
 #pragma unroll
   for (int i = 0; i < EPL; ++i) {
     const int x = residue_t<LIMBS>(Lr[i], t, tab);
     const int y = residue_t<LIMBS>(Li[i], t, tab);
-    const int s = residue_sum(x, y, t, p);
-    const int sh = 8 * (i & 3);
-    b[0][i >> 2] |= (uint32_t)(uint8_t)(int8_t)x << sh;
-    b[1][i >> 2] |= (uint32_t)(uint8_t)(int8_t)y << sh;
-    b[2][i >> 2] |= (uint32_t)(uint8_t)(int8_t)s << sh;
+    v[0][i] = (uint32_t)x;
+    v[1][i] = (uint32_t)y;
+    v[2][i] = (uint32_t)residue_sum(x, y, t, p);
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) w[c] = make_uint2(b[c][0], b[c][1]);
+  for (int c = 0; c < 3; ++c)
+    w[c] = make_uint2(pack_low_bytes(v[c][0], v[c][1], v[c][2], v[c][3]),
+                      pack_low_bytes(v[c][4], v[c][5], v[c][6], v[c][7]));
 }
 
 // Strided complex vectors (rows of column-major A).  A block covers 32

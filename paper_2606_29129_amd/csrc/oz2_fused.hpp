@@ -169,13 +169,9 @@ __global__ __launch_bounds__(256) void k234_fused(
       __builtin_amdgcn_sched_barrier(0);
       uint32_t w[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t b = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          b |= ((uint32_t)(uint8_t)(int8_t)fuse_residue<t>(L[4 * q + i])) << (8 * i);
-        w[q] = b;
-      }
+      for (int q = 0; q < 4; ++q)
+        w[q] = pack_low_bytes(fuse_residue<t>(L[4 * q]), fuse_residue<t>(L[4 * q + 1]),
+                              fuse_residue<t>(L[4 * q + 2]), fuse_residue<t>(L[4 * q + 3]));
       const v4i af = {(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

@@ -72,23 +72,18 @@ __device__ __forceinline__ void pack_residues(const Limbs<LIMBS> (&L)[EPT], int 
                                               uint32_t (&w)[EPT / 4]) {
   if (t == 0) {  // modulus 0 is 256
 #pragma unroll
-    for (int q = 0; q < EPT / 4; ++q) {
-      uint32_t b = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) b |= ((uint32_t)(uint8_t)residue_256<LIMBS>(L[4 * q + i])) << (8 * i);
-      w[q] = b;
-    }
+    for (int q = 0; q < EPT / 4; ++q)
+      w[q] = pack_low_bytes(residue_256<LIMBS>(L[4 * q]), residue_256<LIMBS>(L[4 * q + 1]),
+                            residue_256<LIMBS>(L[4 * q + 2]), residue_256<LIMBS>(L[4 * q + 3]));
   } else {
     const double p = tab->p[t], ip = tab->inv_p[t];
     const double* pw = tab->powL[t];
 #pragma unroll
-    for (int q = 0; q < EPT / 4; ++q) {
-      uint32_t b = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        b |= ((uint32_t)(uint8_t)(int8_t)residue_odd<LIMBS>(L[4 * q + i], pw, p, ip)) << (8 * i);
-      w[q] = b;
-    }
+    for (int q = 0; q < EPT / 4; ++q)
+      w[q] = pack_low_bytes(residue_odd<LIMBS>(L[4 * q], pw, p, ip),
+                            residue_odd<LIMBS>(L[4 * q + 1], pw, p, ip),
+                            residue_odd<LIMBS>(L[4 * q + 2], pw, p, ip),
+                            residue_odd<LIMBS>(L[4 * q + 3], pw, p, ip));
   }
 }
 

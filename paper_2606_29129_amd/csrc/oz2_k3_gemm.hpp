@@ -190,21 +190,19 @@ __device__ __forceinline__ void tile_epilogue(
       uint32_t w[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint32_t b = 0;
+        uint32_t u[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          int c = acc[i][j][4 * q + e];
-          uint32_t u;
+          const int c = acc[i][j][4 * q + e];
           if (is256) {
-            u = (uint32_t)c & 0xFFu;
+            u[e] = (uint32_t)c;                   // the low byte is kept
           } else {
-            double y = (double)c;
-            double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
-            u = (uint32_t)(int)r & 0xFFu;         // its two's-complement byte
+            const double y = (double)c;
+            const double r = fma(-rint(y * ip), p, y);  // exact, |r| <= (p-1)/2
+            u[e] = (uint32_t)(int)r;                    // its two's-complement byte is kept
           }
-          b |= u << (8 * e);
         }
-        w[q] = b;
+        w[q] = pack_low_bytes(u[0], u[1], u[2], u[3]);
       }
       const int64_t bi = (int64_t)tm * (BM / 32) + wm * (TM) + i;
       const int64_t bj = (int64_t)tn * (BN / 32) + wn * (TN) + j;

@@ -14,6 +14,19 @@
 
 namespace oz2 {
 
+// The low bytes of four 32-bit values in one dword (v0's in byte 0): two
+// byte permutes gather the pairs, a third joins them (three instructions;
+// masking and shifting each byte takes six).
+OZ2_HD uint32_t pack_low_bytes(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t lo = __builtin_amdgcn_perm(v1, v0, 0x0c0c0400u);  // v0.b0, v1.b0, 0, 0
+  const uint32_t hi = __builtin_amdgcn_perm(v3, v2, 0x0c0c0400u);
+  return __builtin_amdgcn_perm(hi, lo, 0x05040100u);             // lo.b0, lo.b1, hi.b0, hi.b1
+#else
+  return (v0 & 0xFFu) | ((v1 & 0xFFu) << 8) | ((v2 & 0xFFu) << 16) | ((v3 & 0xFFu) << 24);
+#endif
+}
+
 OZ2_HD double bits_to_f64(uint64_t u) { return __builtin_bit_cast(double, u); }
 OZ2_HD uint64_t f64_to_bits(double d) { return __builtin_bit_cast(uint64_t, d); }
 OZ2_HD float bits_to_f32(uint32_t u) { return __builtin_bit_cast(float, u); }
