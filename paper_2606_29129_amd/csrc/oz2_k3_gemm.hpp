@@ -11,8 +11,10 @@
 // fragment reads of a 32-row block hit distinct banks) and the next slab's
 // global loads are in flight while the current one feeds the MFMAs.
 //
-// Epilogue: |C_t| <= k * 128^2 fits INT32 for k <= 2^17 (Section 2.2).  The
-// product is reduced to U_t = rmod(C_t, p_t) in [-(p_t-1)/2, (p_t-1)/2] (for
+// Epilogue: for odd p_t, |C_t| <= k 127^2 < 2^31 for k <= 2^17 (Section 2.2),
+// so the INT32 sum is exact; plane 0 (p = 256, residues in [-128, 127]) can
+// reach k 128^2 = 2^31 there and is exact modulo 2^32, which keeps its low
+// byte -- all that is used of it -- exact.  The product is reduced to U_t = rmod(C_t, p_t) in [-(p_t-1)/2, (p_t-1)/2] (for
 // p_t = 256 the low byte, in [-128, 127]) and stored as one signed byte
 // per entry, in 32 x 32 blocks laid out in the MFMA accumulator order: block
 // (bi, bj) of plane t is 1024 contiguous bytes at ((t Nb + bj) Mb + bi) * 1024

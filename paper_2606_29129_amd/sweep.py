@@ -462,6 +462,7 @@ def sweep_complex(args):
             oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
             fn = oz.ozaki2_cgemm if single else oz.ozaki2_zgemm
             Ns = [int(x) for x in (args.cNs if single else args.zNs).split(",")]
+            oz.ensure_workspace(max(oz.ozaki2_zgemm_workspace_size(S, S, S, N, 0) for N in Ns))
             for N in Ns:
                 def run():
                     rc = fn(S, S, S, A_cm, S, B_cm, S, C_cm, S, N, 0)
