@@ -6,6 +6,7 @@
     python -m paper_2606_29129_amd.sweep accuracy [--block 512]
     python -m paper_2606_29129_amd.sweep sgemm [--sizes 4096,8192,16384]
     python -m paper_2606_29129_amd.sweep complex [--sizes 4096,8192] [--zNs ...] [--cNs ...]
+    python -m paper_2606_29129_amd.sweep alpha [--alpha-sizes 1024,16384] [--alpha-cases ...]
 
 Every result is one JSON line on stdout.
 
@@ -30,6 +31,16 @@ Every result is one JSON line on stdout.
 
 * ``sgemm``: binary32 emulation (Section 5) over sizes for N = 5..9 beside
   native binary32 ``torch.matmul``.
+* ``alpha``: the scale experiment of Sections 3.2 and 4: fixed matrices
+  Ahat, Bhat (random with phi in the list, or all ones) and the inputs
+  A = 2^s Ahat, B = 2^s Bhat for s = -10..10; the maximum relative and
+  componentwise error of the revised fast mode, the original fast mode
+  (Algorithm 1) and accurate mode at one N, and of native FP64, on a
+  sampled block (the reference is the block's double-double product times
+  4^s, exact); over the whole matrix, the original and accurate modes'
+  largest relative and componentwise distance from the revised result and
+  the number of entries more than 0.1% away from it (failed CRT recoveries
+  show up there).
 * ``complex``: ZGEMM and CGEMM emulation (8mnk/t) over sizes and N beside
   native complex ``torch.matmul``; errors per part against a double-double
   reference (Re = [Re A, -Im A][Re B; Im B], Im = [Re A, Im A][Im B; Re B]).
@@ -485,10 +496,74 @@ def sweep_complex(args):
         torch.cuda.empty_cache()
 
 
+def sweep_alpha(args):
+    import torch
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.alpha_sizes.split(",")]
+    cases = args.alpha_cases.split(",")
+    N = args.alpha_N
+    rng = np.random.default_rng(4)
+    modes = ((0, "revised"), (1, "original"), (2, "accurate"))
+    for S in sizes:
+        for case in cases:
+            if case == "ones":
+                Ah = torch.ones((S, S), dtype=torch.float64, device=dev)
+                Bh = torch.ones((S, S), dtype=torch.float64, device=dev)
+            else:
+                phi = float(case)
+                Ah = inputs.ozaki_matrix_torch(S, S, phi, 0, 0, dev)
+                Bh = inputs.ozaki_matrix_torch(S, S, phi, 0, 1, dev)
+            rows = np.sort(rng.choice(S, args.sample, replace=False))
+            cols = np.sort(rng.choice(S, args.sample, replace=False))
+            rt, ct = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+            ref, absAB = _block(Ah[rt].cpu().numpy(), Bh[:, ct].cpu().numpy(), rows, cols)
+            P = Problem(torch, Ah, Bh, N)
+            A0, B0 = P.A_cm.clone(), P.B_cm.clone()
+            # (|A||B|)^T over the whole matrix, in the layout of C^T = B^T A^T
+            absT = torch.matmul(B0.abs(), A0.abs())
+            for s in range(-10, 11):
+                a = 2.0 ** s          # exact scalings: no entry leaves the normal range
+                torch.mul(A0, a, out=P.A_cm)
+                torch.mul(B0, a, out=P.B_cm)
+                sc = a * a
+                rs = ((ref[0] * sc, ref[1] * sc), absAB * sc)
+                out = dict(leg="alpha", m=S, n=S, k=S, case=case, s=s, N=N,
+                           sample=f"{args.sample}x{args.sample} block")
+                Crev = None
+                for md, name in modes:
+                    P.run(N, md)
+                    torch.cuda.synchronize()
+                    out[name] = errors(P.C_block(rows, cols), *rs)
+                    if Crev is None:
+                        Crev = P.C_cm.clone()
+                    else:
+                        # over every entry, against the revised result (its
+                        # sampled errors are at the binary64 floor): the
+                        # largest relative and componentwise distances, and
+                        # the entries more than 0.1% away from it
+                        d = (P.C_cm - Crev).abs()
+                        pos = absT > 0
+                        nz = Crev != 0
+                        rel = d[nz] / Crev[nz].abs()
+                        out[name]["full_max_rel_vs_revised"] = float(rel.max())
+                        out[name]["full_max_cw_vs_revised"] = float((d[pos] / (absT[pos] * sc)).max())
+                        out[name]["full_entries_off_1e-3"] = int((rel > 1e-3).sum())
+                        del d, pos, nz, rel
+                del Crev
+                Cn = torch.matmul(Ah * a, Bh * a)
+                out["native"] = errors(Cn.index_select(0, rt).index_select(1, ct).cpu().numpy(),
+                                       *rs)
+                del Cn
+                _emit(out)
+            P.release()
+            del A0, B0, Ah, Bh, absT
+            torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy", "sgemm",
-                                    "complex"])
+                                    "complex", "alpha"])
     ap.add_argument("--sizes", default="1024,4096,8192,16384")
     ap.add_argument("--phis", default="0.5,1,2,4")
     ap.add_argument("--Ns", default="12,14,16,18,20")
@@ -500,9 +575,14 @@ def main(argv=None):
     ap.add_argument("--scale-size", type=int, default=4096)
     ap.add_argument("--zNs", default="12,14,16,18", help="N list of the ZGEMM runs")
     ap.add_argument("--cNs", default="5,6,7,8", help="N list of the CGEMM runs")
+    ap.add_argument("--alpha-sizes", default="1024,16384")
+    ap.add_argument("--alpha-cases", default="0.5,1,2,3,4,ones",
+                    help="phi values of Ahat, Bhat, or 'ones' (all-ones matrices)")
+    ap.add_argument("--alpha-N", type=int, default=20)
     a = ap.parse_args(argv)
     {"throughput": sweep_throughput, "shapes": sweep_shapes, "scale": sweep_scale,
-     "accuracy": sweep_accuracy, "sgemm": sweep_sgemm, "complex": sweep_complex}[a.leg](a)
+     "accuracy": sweep_accuracy, "sgemm": sweep_sgemm, "complex": sweep_complex,
+     "alpha": sweep_alpha}[a.leg](a)
 
 
 if __name__ == "__main__":
