@@ -7,6 +7,7 @@
     python -m paper_2606_29129_amd.sweep sgemm [--sizes 4096,8192,16384]
     python -m paper_2606_29129_amd.sweep complex [--sizes 4096,8192] [--zNs ...] [--cNs ...]
     python -m paper_2606_29129_amd.sweep alpha [--alpha-sizes 1024,16384] [--alpha-cases ...]
+    python -m paper_2606_29129_amd.sweep modes [--alpha-sizes 1024,16384]
 
 Every result is one JSON line on stdout.
 
@@ -41,6 +42,14 @@ Every result is one JSON line on stdout.
   largest relative and componentwise distance from the revised result and
   the number of entries more than 0.1% away from it (failed CRT recoveries
   show up there).
+* ``modes``: the accuracy comparison of Section 5.1: DGEMM for N = 9..20
+  at phi = 0.5, 1, 2, 3, 4 and SGEMM (binary32-rounded inputs) for N = 3..12
+  at phi = 0, 0.5, 1, 1.5, each in the revised fast mode, the original fast
+  mode and accurate mode, beside native ``torch.matmul``: the error of a
+  sampled block against its double-double product, and over the whole
+  matrix the maximum relative distance from the revised binary64 emulation
+  at N = 20 of the same inputs (whose sampled error is at the binary64
+  floor; for SGEMM far below binary32's).
 * ``complex``: ZGEMM and CGEMM emulation (8mnk/t) over sizes and N beside
   native complex ``torch.matmul``; errors per part against a double-double
   reference (Re = [Re A, -Im A][Re B; Im B], Im = [Re A, Im A][Im B; Re B]).
@@ -560,10 +569,60 @@ def sweep_alpha(args):
             torch.cuda.empty_cache()
 
 
+def sweep_modes(args):
+    import torch
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in args.alpha_sizes.split(",")]
+    rng = np.random.default_rng(5)
+    legs = ((False, (0.5, 1.0, 2.0, 3.0, 4.0), range(9, 21)),
+            (True, (0.0, 0.5, 1.0, 1.5), range(3, 13)))
+    modes = ((0, "revised"), (1, "original"), (2, "accurate"))
+    for S in sizes:
+        for single, phis, Ns in legs:
+            for phi in phis:
+                A = inputs.ozaki_matrix_torch(S, S, phi, 0, 0, dev)
+                B = inputs.ozaki_matrix_torch(S, S, phi, 0, 1, dev)
+                if single:      # the binary32 inputs, held exactly in binary64
+                    A, B = A.float().double(), B.float().double()
+                rows = np.sort(rng.choice(S, args.sample, replace=False))
+                cols = np.sort(rng.choice(S, args.sample, replace=False))
+                rt, ct = torch.as_tensor(rows, device=dev), torch.as_tensor(cols, device=dev)
+                ref, absAB = _block(A[rt].cpu().numpy(), B[:, ct].cpu().numpy(), rows, cols)
+                P = Problem(torch, A, B, 20)
+                P.run(20)
+                Cref = P.C_cm.clone()               # C^T, revised binary64 emulation, N = 20
+                P.release()
+                nz = Cref != 0
+                absref = Cref[nz].abs()
+
+                def full_rel(CT):
+                    return float(((CT.double() - Cref).abs()[nz] / absref).max())
+
+                base = dict(leg="modes", m=S, n=S, k=S, phi=phi,
+                            precision="fp32" if single else "fp64",
+                            sample=f"{args.sample}x{args.sample} block")
+                Cn = (torch.matmul(A.float(), B.float()) if single else torch.matmul(A, B))
+                _emit(dict(base, method="native torch.matmul",
+                           full_max_rel_vs_N20=full_rel(Cn.t()),
+                           **errors(Cn.index_select(0, rt).index_select(1, ct).double()
+                                    .cpu().numpy(), ref, absAB)))
+                del Cn
+                P = Problem(torch, A, B, max(Ns), single=single)
+                for N in Ns:
+                    for md, name in modes:
+                        P.run(N, md)
+                        torch.cuda.synchronize()
+                        _emit(dict(base, method=name, N=N, full_max_rel_vs_N20=full_rel(P.C_cm),
+                                   **errors(P.C_block(rows, cols), ref, absAB)))
+                P.release()
+                del A, B, Cref, nz, absref
+                torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("leg", choices=["throughput", "shapes", "scale", "accuracy", "sgemm",
-                                    "complex", "alpha"])
+                                    "complex", "alpha", "modes"])
     ap.add_argument("--sizes", default="1024,4096,8192,16384")
     ap.add_argument("--phis", default="0.5,1,2,4")
     ap.add_argument("--Ns", default="12,14,16,18,20")
@@ -582,7 +641,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     {"throughput": sweep_throughput, "shapes": sweep_shapes, "scale": sweep_scale,
      "accuracy": sweep_accuracy, "sgemm": sweep_sgemm, "complex": sweep_complex,
-     "alpha": sweep_alpha}[a.leg](a)
+     "alpha": sweep_alpha, "modes": sweep_modes}[a.leg](a)
 
 
 if __name__ == "__main__":

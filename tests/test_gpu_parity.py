@@ -275,6 +275,18 @@ def test_sgemm_parity(m, n, k, phi, N):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("m,n,k,phi,N", [(130, 70, 300, 1.5, 7), (40, 33, 129, 0.5, 4)])
+def test_sgemm_original_and_accurate_mode_parity(m, n, k, phi, N, mode):
+    """SGEMM emulation with Algorithm 1's scaling and with accurate mode's
+    (Section 2.3) scale estimate: equal to the oracle bit for bit."""
+    A, B = inputs.problem(m, n, k, phi, seed=40 + N + mode)
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    want = ref.sgemm(A32, B32, N, mode)
+    got = _gpu_sgemm(A32, B32, N, mode)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
 @pytest.mark.parametrize("m,n,k,phi,N,seed", [(300, 280, 520, 1.0, 14, 31), (37, 90, 129, 4.0, 20, 32),
                                               (64, 48, 33, 0.5, 8, 33)])
 def test_accurate_mode_parity(m, n, k, phi, N, seed):
