@@ -126,34 +126,43 @@ def errors(C, ref, absAB):
 # --- timing -----------------------------------------------------------------
 
 def _timed(torch, fn, steps, warmup):
+    """Median time of `steps` calls, each between two events on the current
+    stream (no stage events inside them), then the mean per-stage times of
+    `steps` further calls made with stage timing on."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    oz._check("ozaki2_set_timing", oz.ozaki2_set_timing(1))
     evs[0].record(stream)
     for s in range(steps):
         fn()
         evs[s + 1].record(stream)
     torch.cuda.synchronize()
+    per = sorted(evs[s].elapsed_time(evs[s + 1]) for s in range(steps))
+    oz._check("ozaki2_set_timing", oz.ozaki2_set_timing(1))
+    for _ in range(steps):
+        fn()
     stage_ms, calls = oz.ozaki2_get_stage_times()
     oz.ozaki2_set_timing(0)
-    per = sorted(evs[s].elapsed_time(evs[s + 1]) for s in range(steps))
     st = {name: round(v / max(calls, 1), 4) for name, v in zip(oz.STAGE_NAMES, stage_ms)}
     return per[len(per) // 2], st
 
 
-def _native_ms(torch, A, B, steps=3):
+def _native_ms(torch, A, B, steps=10):
+    """Median time of `steps` torch.matmul calls (each between two events),
+    after one warm-up call; also returns the product."""
     C = torch.matmul(A, B)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for s in range(steps):
         torch.matmul(A, B, out=C)
-    e1.record()
+        evs[s + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps, C
+    per = sorted(evs[s].elapsed_time(evs[s + 1]) for s in range(steps))
+    return per[len(per) // 2], C
 
 
 class Problem:
@@ -626,7 +635,7 @@ def main(argv=None):
     ap.add_argument("--sizes", default="1024,4096,8192,16384")
     ap.add_argument("--phis", default="0.5,1,2,4")
     ap.add_argument("--Ns", default="12,14,16,18,20")
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sample", type=int, default=32, help="sampled block edge (throughput legs)")
     ap.add_argument("--block", type=int, default=512, help="sampled block edge (accuracy leg)")
