@@ -49,7 +49,9 @@ Every result is one JSON line on stdout.
   sampled block against its double-double product, and over the whole
   matrix the maximum relative distance from the revised binary64 emulation
   at N = 20 of the same inputs (whose sampled error is at the binary64
-  floor; for SGEMM far below binary32's).
+  floor; for SGEMM far below binary32's); and each run's throughput 2mnk/t
+  (median of timed calls) beside native ``torch.matmul``'s, for the
+  accuracy-throughput trade-off of Section 5.3.
 * ``complex``: ZGEMM and CGEMM emulation (8mnk/t) over sizes and N beside
   native complex ``torch.matmul``; errors per part against a double-double
   reference (Re = [Re A, -Im A][Re B; Im B], Im = [Re A, Im A][Im B; Re B]).
@@ -610,18 +612,23 @@ def sweep_modes(args):
                 base = dict(leg="modes", m=S, n=S, k=S, phi=phi,
                             precision="fp32" if single else "fp64",
                             sample=f"{args.sample}x{args.sample} block")
-                Cn = (torch.matmul(A.float(), B.float()) if single else torch.matmul(A, B))
-                _emit(dict(base, method="native torch.matmul",
+                flops = 2.0 * S ** 3
+                Ax, Bx = (A.float(), B.float()) if single else (A, B)
+                nat_ms, Cn = _native_ms(torch, Ax, Bx)
+                _emit(dict(base, method="native torch.matmul", ms=round(nat_ms, 4),
+                           tflops=round(flops / nat_ms / 1e9, 2),
                            full_max_rel_vs_N20=full_rel(Cn.t()),
                            **errors(Cn.index_select(0, rt).index_select(1, ct).double()
                                     .cpu().numpy(), ref, absAB)))
-                del Cn
+                del Cn, Ax, Bx
                 P = Problem(torch, A, B, max(Ns), single=single)
                 for N in Ns:
                     for md, name in modes:
-                        P.run(N, md)
+                        ms, st = _timed(torch, lambda: P.run(N, md), args.steps, args.warmup)
                         torch.cuda.synchronize()
-                        _emit(dict(base, method=name, N=N, full_max_rel_vs_N20=full_rel(P.C_cm),
+                        _emit(dict(base, method=name, N=N, ms=round(ms, 4),
+                                   tflops=round(flops / ms / 1e9, 2), stage_ms=st,
+                                   full_max_rel_vs_N20=full_rel(P.C_cm),
                                    **errors(P.C_block(rows, cols), ref, absAB)))
                 P.release()
                 del A, B, Cref, nz, absref
