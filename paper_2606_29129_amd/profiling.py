@@ -5,6 +5,8 @@
         --workload "m=16384 n=16384 k=16384 N=14" --copy-bytes B > traffic.txt
     python -m paper_2606_29129_amd.profiling counters COMMAND DIR... --ms T --ops X
     python -m paper_2606_29129_amd.profiling batch [--replays R] [--timing]
+    python -m paper_2606_29129_amd.profiling zeros [--size S] [--N N] [--phi P] [--modes 0,1]
+    python -m paper_2606_29129_amd.profiling clock DIR COMMAND --labels a,b,...
 
 ``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
 --stats --output-format csv`` writes and prints a short markdown table of the
@@ -15,7 +17,13 @@ and scales it by what the same counter reads for a plain streaming kernel of
 known size in the same run (``bench.py --traffic-calibration``: one
 ``torch.abs`` over a float64 tensor of ``--copy-bytes`` bytes, which reads and
 writes that many bytes once).  The result is the file that ``bench.py`` reads
-to fill ``roofline.traffic``.
+to fill ``roofline.traffic``.  ``zeros`` runs emulated DGEMMs of one
+workload in several scaling modes (operands generated on the device, a few
+calls per mode, twice over) and prints the fraction of zero entries of the
+scaled integers A'; ``clock`` reads a ``rocprofv3 --kernel-trace --pmc
+GRBM_GUI_ACTIVE SQ_BUSY_CU_CYCLES SQ_VALU_MFMA_BUSY_CYCLES`` run of it and
+prints, per INT8 GEMM dispatch, its duration, the shader clock it ran at and
+the MFMA pipes' busy fraction.
 """
 from __future__ import annotations
 
@@ -266,6 +274,51 @@ def run_batch(replays=3, count=256, seed=0, target=1e-15, timing=False):
                                   for n, v in zip(oz.STAGE_NAMES, st)}, flush=True)
 
 
+def run_zeros(size=16384, N=9, phi=4.0, modes=(0, 1), reps=3):
+    """Driver for the clock-by-data measurement: `reps` calls per mode, the
+    mode sequence run twice, then the zero fraction of A' per mode."""
+    import torch
+    from paper_2606_29129_amd import inputs
+    from paper_2606_29129_amd.sweep import Problem, zero_fraction
+    dev = torch.device("cuda:0")
+    A = inputs.ozaki_matrix_torch(size, size, phi, 0, 0, dev)
+    B = inputs.ozaki_matrix_torch(size, size, phi, 0, 1, dev)
+    P = Problem(torch, A, B, N)
+    for mode in list(modes) * 2:
+        for _ in range(reps):
+            P.run(N, mode)
+        torch.cuda.synchronize()
+        eA, _ = P.exponents(N, mode)
+        print(f"m=n=k={size} phi={phi} N={N} mode {mode}: {reps} calls; zero fraction of A' "
+              f"{zero_fraction(torch, A, eA, 0):.4f}", flush=True)
+    P.release()
+
+
+def clock_markdown(d: str, cmd: str, labels, kernel: str = K3_NAME) -> str:
+    """Per dispatch of `kernel` in a --kernel-trace --pmc run: duration (from
+    the counter file's timestamps), shader clock GRBM_GUI_ACTIVE / (8 XCDs x
+    duration), MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (4 SIMDs x
+    SQ_BUSY_CU_CYCLES); labels name the dispatches in order."""
+    per = {}
+    for f in _find(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            k = int(r["Dispatch_Id"])
+            e = per.setdefault(k, {"dur": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = [f"# Shader clock of `{kernel}` by operand data (rocprofv3 --kernel-trace --pmc)", "",
+           "Command (run from the repository root on one MI355X):", "", "```", cmd, "```", "",
+           "| dispatch | label | ms | clock GHz | MFMA busy |", "|---|---|---|---|---|"]
+    for i, k in enumerate(sorted(per)):
+        e = per[k]
+        clk = e["GRBM_GUI_ACTIVE"] / 8 / e["dur"] / 1e9
+        busy = e["SQ_VALU_MFMA_BUSY_CYCLES"] / (4 * e["SQ_BUSY_CU_CYCLES"])
+        lab = labels[i] if i < len(labels) else "?"
+        out.append(f"| {k} | {lab} | {e['dur'] * 1e3:.2f} | {clk:.3f} | {busy:.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -289,8 +342,22 @@ def main(argv=None):
     b.add_argument("--replays", type=int, default=3)
     b.add_argument("--count", type=int, default=256)
     b.add_argument("--timing", action="store_true", help="stage events instead of the graph")
+    z = sub.add_parser("zeros", help="DGEMMs of one workload in several modes; zero fractions")
+    z.add_argument("--size", type=int, default=16384)
+    z.add_argument("--N", type=int, default=9)
+    z.add_argument("--phi", type=float, default=4.0)
+    z.add_argument("--modes", default="0,1")
+    z.add_argument("--reps", type=int, default=3)
+    k = sub.add_parser("clock")
+    k.add_argument("dir")
+    k.add_argument("command")
+    k.add_argument("--labels", default="")
     a = ap.parse_args(argv)
-    if a.what == "batch":
+    if a.what == "zeros":
+        run_zeros(a.size, a.N, a.phi, tuple(int(x) for x in a.modes.split(",")), a.reps)
+    elif a.what == "clock":
+        sys.stdout.write(clock_markdown(a.dir, a.command, a.labels.split(",") if a.labels else []))
+    elif a.what == "batch":
         run_batch(a.replays, a.count, timing=a.timing)
     elif a.what == "counters":
         sys.stdout.write(counters_markdown(a.dirs, a.command, a.kernel, a.ms, a.ops))

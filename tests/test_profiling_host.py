@@ -71,3 +71,23 @@ def test_code_hash_ignores_comments_only(tmp_path):
     c.write_text("int f() {\n  return 2;\n}\n")
     assert profiling.source_sha(str(a)) == profiling.source_sha(str(b))
     assert profiling.source_sha(str(a)) != profiling.source_sha(str(c))
+
+
+def test_clock_by_dispatch(tmp_path):
+    """Per-dispatch clock = GRBM_GUI_ACTIVE / 8 XCDs / duration and MFMA busy
+    = MFMA busy cycles / (4 SIMDs x CU busy cycles), from the timestamps of
+    the counter file; other kernels are ignored; labels follow the order."""
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value",
+           "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for disp, ns, grbm, mfma in ((7, 10_000_000, 8 * 2.0e9 * 0.01, 0.5), (9, 5_000_000, 8 * 1.0e9 * 0.005, 0.25)):
+        rows += [[disp, K3, "GRBM_GUI_ACTIVE", grbm, 100, 100 + ns],
+                 [disp, K3, "SQ_BUSY_CU_CYCLES", 1000.0, 100, 100 + ns],
+                 [disp, K3, "SQ_VALU_MFMA_BUSY_CYCLES", 4 * 1000.0 * mfma, 100, 100 + ns]]
+    rows.append([8, COPY, "GRBM_GUI_ACTIVE", 1.0, 0, 10])
+    _write(tmp_path / "p" / "1_counter_collection.csv", hdr, rows)
+    md = profiling.clock_markdown(str(tmp_path / "p"), "the command", ["a", "b"])
+    assert "the command" in md
+    assert "| 7 | a | 10.00 | 2.000 | 0.500 |" in md
+    assert "| 9 | b | 5.00 | 1.000 | 0.250 |" in md
+    assert "| 8 |" not in md
