@@ -79,7 +79,7 @@ __device__ __forceinline__ int fuse_residue(const Limbs<2>& L) {
   } else {
     constexpr double p = (double)kModuli[t], ip = 1.0 / (double)kModuli[t];
     constexpr double c1 = fuse_pow40(kModuli[t]);
-    const double y = fma(L.x[1], c1, L.x[0]);
+    const double y = fma(L.x[1], sconst(c1), L.x[0]);
     const double q = rint(y * ip);
     return (int)fma(-q, p, y);
   }

@@ -60,7 +60,7 @@ OZ2_HD int residue_odd(const Limbs<LIMBS>& L, const double* pw, double p, double
 template <int LIMBS>
 OZ2_HD int residue_256(const Limbs<LIMBS>& L) {
   const double x = L.x[0];
-  const double lo = fma(-256.0, floor(x * (1.0 / 256.0)), x);   // in [0, 256), exact
+  const double lo = fma(sconst(-256.0), floor(ldexp(x, -8)), x);   // in [0, 256), exact
   return (int)(int8_t)(uint8_t)(int)lo;
 }
 

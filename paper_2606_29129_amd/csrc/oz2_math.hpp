@@ -14,6 +14,21 @@
 
 namespace oz2 {
 
+// A binary64 constant held in a scalar register pair.  gfx9's three-operand
+// (VOP3) encoding takes no literal, so an FMA with a constant factor whose
+// addend stays live was encoded in the two-operand form with a literal,
+// after a copy of the addend: one extra move per use.  From a scalar
+// register the FMA is a single VOP3 instruction.
+OZ2_HD double sconst(double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r;
+  asm("s_mov_b64 %0, %1" : "=s"(r) : "s"(c));
+  return r;
+#else
+  return c;
+#endif
+}
+
 // The low bytes of four 32-bit values in one dword (v0's in byte 0): two
 // byte permutes gather the pairs, a third joins them (three instructions;
 // masking and shifting each byte takes six).

@@ -6,6 +6,7 @@
     python -m paper_2606_29129_amd.profiling counters COMMAND DIR... --ms T --ops X
     python -m paper_2606_29129_amd.profiling batch [--replays R] [--timing]
     python -m paper_2606_29129_amd.profiling zeros [--size S] [--N N] [--phi P] [--modes 0,1]
+    python -m paper_2606_29129_amd.profiling shape --m M --n N --k K [--N NM] [--calls C]
     python -m paper_2606_29129_amd.profiling clock DIR COMMAND --labels a,b,...
 
 ``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
@@ -294,6 +295,26 @@ def run_zeros(size=16384, N=9, phi=4.0, modes=(0, 1), reps=3):
     P.release()
 
 
+def run_shape(m, n, k, N=14, phi=1.0, calls=5):
+    """Driver for counter runs of one DGEMM shape: operands generated on the
+    host and copied to the GPU (the process's only kernels are the library's
+    and copies), `calls` calls in the revised mode."""
+    import torch
+    from paper_2606_29129_amd import inputs
+    from paper_2606_29129_amd import ozaki2 as oz
+    dev = torch.device("cuda:0")
+    A, B = inputs.problem(m, n, k, phi, seed=0)
+    A_cm = torch.from_numpy(A.T.copy()).to(dev)
+    B_cm = torch.from_numpy(B.T.copy()).to(dev)
+    C_cm = torch.empty((n, m), dtype=torch.float64, device=dev)
+    oz.ozaki2_set_stream(torch.cuda.current_stream().cuda_stream)
+    oz.ensure_workspace(oz.ozaki2_workspace_size(m, n, k, N, 0))
+    for _ in range(calls):
+        oz._check("ozaki2_dgemm", oz.ozaki2_dgemm(m, n, k, A_cm, m, B_cm, k, C_cm, m, N, 0))
+    torch.cuda.synchronize()
+    print(f"{calls} calls of {m}x{n}x{k}, N={N}, phi={phi}", flush=True)
+
+
 def clock_markdown(d: str, cmd: str, labels, kernel: str = K3_NAME) -> str:
     """Per dispatch of `kernel` in a --kernel-trace --pmc run: duration (from
     the counter file's timestamps), shader clock GRBM_GUI_ACTIVE / (8 XCDs x
@@ -348,12 +369,21 @@ def main(argv=None):
     z.add_argument("--phi", type=float, default=4.0)
     z.add_argument("--modes", default="0,1")
     z.add_argument("--reps", type=int, default=3)
+    h = sub.add_parser("shape", help="DGEMMs of one shape, host-generated operands")
+    h.add_argument("--m", type=int, required=True)
+    h.add_argument("--n", type=int, required=True)
+    h.add_argument("--k", type=int, required=True)
+    h.add_argument("--N", type=int, default=14)
+    h.add_argument("--phi", type=float, default=1.0)
+    h.add_argument("--calls", type=int, default=5)
     k = sub.add_parser("clock")
     k.add_argument("dir")
     k.add_argument("command")
     k.add_argument("--labels", default="")
     a = ap.parse_args(argv)
-    if a.what == "zeros":
+    if a.what == "shape":
+        run_shape(a.m, a.n, a.k, a.N, a.phi, a.calls)
+    elif a.what == "zeros":
         run_zeros(a.size, a.N, a.phi, tuple(int(x) for x in a.modes.split(",")), a.reps)
     elif a.what == "clock":
         sys.stdout.write(clock_markdown(a.dir, a.command, a.labels.split(",") if a.labels else []))
