@@ -102,7 +102,9 @@ __global__ __launch_bounds__(256) void k234_fused(
   const int64_t row0 = (int64_t)blockIdx.x * kFuseRows + wave * 16;
   const int64_t arow = row0 + (lane & 15);           // the row of A this lane converts
   const bool rowok = arow < m;
-  const int32_t ea = rowok ? eA[arow] : 0;
+  // rows beyond m convert to zero through the non-finite sentinel (their
+  // outputs are never written)
+  const int32_t ea = rowok ? eA[arow] : kExpNonFinite;
   const T* Ap = A + (rowok ? arow : 0);               // clamped: every load in bounds
   const int kq = (lane >> 4) * 16;                    // this lane's k bytes in a step
 
@@ -116,14 +118,22 @@ __global__ __launch_bounds__(256) void k234_fused(
     for (int t = 0; t < NP; ++t)
       load_lds16(RB + (int64_t)t * Np * Kp + boff + k0, lds[buf] + t * PB + wave * 64 * 16);
   };
-  // A values of a step: 16 consecutive k of one row; out-of-range k reads
-  // the last column (in bounds) and the value is zeroed when used.
+  // A values of a step: 16 consecutive k of one row, lda apart.  Only the
+  // last step can run past k: there out-of-range k reads the last column
+  // (in bounds) and the value is zeroed when used.
   auto load_a = [&](int64_t k0, double (&raw)[16]) {
+    const int64_t kb = k0 + kq;
+    if (kb + 16 <= k) {
+      const T* p = Ap + kb * lda;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int64_t kk = k0 + kq + j;
-      const int64_t kc = kk < k ? kk : k - 1;
-      raw[j] = (double)__builtin_nontemporal_load(Ap + kc * lda);
+      for (int j = 0; j < 16; ++j) raw[j] = (double)__builtin_nontemporal_load(p + j * lda);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int64_t kk = kb + j;
+        const int64_t kc = kk < k ? kk : k - 1;
+        raw[j] = (double)__builtin_nontemporal_load(Ap + kc * lda);
+      }
     }
   };
 
@@ -140,10 +150,14 @@ __global__ __launch_bounds__(256) void k234_fused(
   for (int s = 0; s < nsteps; ++s) {
     const int buf = s & 1;
     const int64_t k0 = (int64_t)s * kFuseK;
+    if (k0 + kq + 16 > k) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (k0 + kq + j >= k) raw[j] = 0.0;
+    }
     Limbs<2> L[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      L[j] = make_limbs<2>((rowok && k0 + kq + j < k) ? raw[j] : 0.0, ea);
+    for (int j = 0; j < 16; ++j) L[j] = make_limbs<2>(raw[j], ea);
     const bool more = s + 1 < nsteps;
     if (more) {
       load_a(k0 + kFuseK, raw);
