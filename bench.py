@@ -562,7 +562,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the emulated DGEMM is a "
+        print("bench.py: the benchmark runs on one GPU only (the emulated DGEMM is a "
               "single-GPU kernel pipeline); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 

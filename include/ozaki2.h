@@ -81,7 +81,7 @@ extern "C" {
                                   ozaki2_set_workspace_policy), or the
                                   library's own allocation failed */
 #define OZ2_ERR_HIP          3 /* a HIP runtime call failed */
-#define OZ2_ERR_UNSUPPORTED  4 /* valid request this build does not support */
+#define OZ2_ERR_UNSUPPORTED  4 /* valid request the library does not support */
 #define OZ2_ERR_TOO_LARGE    5 /* a size overflows the library's indexing */
 #define OZ2_ERR_SCRATCH_TOO_SMALL 6 /* ozaki2_dgemm_noalloc: the problem needs
                                        more than OZ2_NOALLOC_SCRATCH_BYTES */
