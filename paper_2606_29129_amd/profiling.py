@@ -8,6 +8,7 @@
     python -m paper_2606_29129_amd.profiling zeros [--size S] [--N N] [--phi P] [--modes 0,1]
     python -m paper_2606_29129_amd.profiling shape --m M --n N --k K [--N NM] [--calls C]
     python -m paper_2606_29129_amd.profiling clock DIR COMMAND --labels a,b,...
+    python -m paper_2606_29129_amd.profiling issue COMMAND DIR... [--units NAME=COUNT ...]
 
 ``stats`` reads the ``*kernel_stats.csv`` that ``rocprofv3 --kernel-trace
 --stats --output-format csv`` writes and prints a short markdown table of the
@@ -340,6 +341,47 @@ def clock_markdown(d: str, cmd: str, labels, kernel: str = K3_NAME) -> str:
     return "\n".join(out) + "\n"
 
 
+def issue_markdown(dirs, cmd: str, units=None) -> str:
+    """Per kernel of ``--kernel-trace --pmc`` runs (counter files with
+    timestamps): mean duration, shader clock, VALU wave instructions, the
+    VALU issue fraction (4 cycles per wave instruction over 1024 SIMDs'
+    cycles at that clock), and the s_waitcnt fraction of wave cycles when
+    those counters were collected.  `units` maps a kernel-name fragment to a
+    unit count (entries, outputs) for lane-operations per unit."""
+    per = defaultdict(dict)
+    for d in dirs:
+        for f in _find(d, "counter_collection.csv"):
+            for r in csv.DictReader(open(f)):
+                key = (d, int(r["Dispatch_Id"]))
+                e = per[key]
+                e["name"] = _short(r["Kernel_Name"])
+                e["dur"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+                e[r["Counter_Name"]] = float(r["Counter_Value"])
+    agg = defaultdict(lambda: defaultdict(list))
+    for e in per.values():
+        for c, v in e.items():
+            if c != "name":
+                agg[e["name"]][c].append(v)
+    out = ["# VALU issue and waits of the element-wise kernels (rocprofv3 --pmc)", "",
+           "Command (run from the repository root on one MI355X; one run per counter group):",
+           "", "```", cmd, "```", "",
+           "| kernel | ms | clock GHz | VALU wave instructions | lane-ops per unit | VALU issue | "
+           "waves in s_waitcnt |", "|---|---|---|---|---|---|---|"]
+    for name in sorted(agg):
+        m = {c: sum(v) / len(v) for c, v in agg[name].items()}
+        clk = m["GRBM_GUI_ACTIVE"] / 8 / m["dur"] if "GRBM_GUI_ACTIVE" in m else float("nan")
+        valu = m.get("SQ_INSTS_VALU", float("nan"))
+        issue = valu * 4 / 1024 / (clk * m["dur"])
+        wait = (m["SQ_WAIT_ANY"] / m["SQ_WAVE_CYCLES"]) if "SQ_WAIT_ANY" in m else float("nan")
+        per_unit = "-"
+        for frag, cnt in (units or {}).items():
+            if frag in name:
+                per_unit = f"{valu * 64 / cnt:.0f}"
+        out.append(f"| `{name}` | {m['dur'] * 1e3:.3f} | {clk / 1e9:.2f} | {valu:.3e} | {per_unit} | "
+                   f"{issue:.2f} | {wait:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="what", required=True)
@@ -380,8 +422,15 @@ def main(argv=None):
     k.add_argument("dir")
     k.add_argument("command")
     k.add_argument("--labels", default="")
+    i = sub.add_parser("issue")
+    i.add_argument("command")
+    i.add_argument("dirs", nargs="+")
+    i.add_argument("--units", nargs="*", default=[], help="kernel fragment=count")
     a = ap.parse_args(argv)
-    if a.what == "shape":
+    if a.what == "issue":
+        units = {u.split("=")[0]: float(u.split("=")[1]) for u in a.units}
+        sys.stdout.write(issue_markdown(a.dirs, a.command, units))
+    elif a.what == "shape":
         run_shape(a.m, a.n, a.k, a.N, a.phi, a.calls)
     elif a.what == "zeros":
         run_zeros(a.size, a.N, a.phi, tuple(int(x) for x in a.modes.split(",")), a.reps)

@@ -91,3 +91,23 @@ def test_clock_by_dispatch(tmp_path):
     assert "| 7 | a | 10.00 | 2.000 | 0.500 |" in md
     assert "| 9 | b | 5.00 | 1.000 | 0.250 |" in md
     assert "| 8 |" not in md
+
+
+def test_issue_summary(tmp_path):
+    """VALU issue = wave instructions x 4 / (1024 SIMDs x clock x duration),
+    clock = GRBM_GUI_ACTIVE / 8 / duration; lane-ops per unit = 64 x wave
+    instructions / units; waits from the second pass."""
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value",
+           "Start_Timestamp", "End_Timestamp"]
+    k4 = "void oz2::k4_crt<4, double>(unsigned char const*, ...)"
+    ns = 1_000_000                                   # 1 ms
+    grbm = 8 * 2.0e9 * 1e-3                          # 2 GHz
+    insts = 0.5 * 1024 * 2.0e9 * 1e-3 / 4            # issue fraction 0.5
+    _write(tmp_path / "a" / "1_counter_collection.csv", hdr, [
+        [3, k4, "GRBM_GUI_ACTIVE", grbm, 0, ns], [3, k4, "SQ_INSTS_VALU", insts, 0, ns]])
+    _write(tmp_path / "b" / "1_counter_collection.csv", hdr, [
+        [3, k4, "SQ_WAIT_ANY", 25.0, 0, ns], [3, k4, "SQ_WAVE_CYCLES", 100.0, 0, ns]])
+    md = profiling.issue_markdown([str(tmp_path / "a"), str(tmp_path / "b")], "cmd",
+                                  {"k4_crt": insts * 64 / 10.0})
+    row = [ln for ln in md.splitlines() if "k4_crt" in ln][0]
+    assert "| 1.000 | 2.00 |" in row and "| 10 | 0.50 | 0.25 |" in row
