@@ -70,12 +70,13 @@ __device__ __forceinline__ void fuse_for(F&& f) {
   fuse_for_impl(f, std::make_integer_sequence<int, NP>{});
 }
 
-// Residue of a' (two limbs) for modulus index t: as residue_256 / residue_odd
-// with the table values of modulus t.
+// Residue of a' (two limbs) for modulus index t, in the low byte of the
+// result (what the packing reads): as residue_256_byte / residue_odd with
+// the table values of modulus t.
 template <int t>
 __device__ __forceinline__ int fuse_residue(const Limbs<2>& L) {
   if constexpr (t == 0) {
-    return residue_256<2>(L);
+    return (int)residue_256_byte<2>(L);
   } else {
     constexpr double p = (double)kModuli[t], ip = 1.0 / (double)kModuli[t];
     constexpr double c1 = fuse_pow40(kModuli[t]);
@@ -83,6 +84,23 @@ __device__ __forceinline__ int fuse_residue(const Limbs<2>& L) {
     const double q = rint(y * ip);
     return (int)fma(-q, p, y);
   }
+}
+
+// Limbs of trunc(a 2^e) for this kernel, whose residues of A are never
+// stored.  A row with a non-finite entry (exponent sentinel) gets a very
+// negative exponent instead, so that its finite entries truncate to 0, and
+// every value is clamped to [-2^78, 2^78] (infinities; NaNs too, since the
+// minimum and maximum return the operand that is not a NaN): its residues
+// are well-defined integers, and its outputs are NaN whatever its products
+// are.  For every other row |a'| < 2^64 (P < 2^128 for N <= 16), so the clamp
+// changes nothing and the limbs are make_limbs<2>'s.
+__device__ __forceinline__ Limbs<2> fuse_limbs(double a, int32_t e) {
+  const double v =
+      __builtin_fmin(__builtin_fmax(trunc(ldexp(a, e)), sconst(-0x1p78)), sconst(0x1p78));
+  Limbs<2> L;
+  L.x[1] = trunc(v * 0x1p-40);
+  L.x[0] = fma(-L.x[1], 0x1p40, v);
+  return L;
 }
 
 // NP = N (a template parameter, so that every accumulator access and product
@@ -104,7 +122,8 @@ __global__ __launch_bounds__(256) void k234_fused(
   const bool rowok = arow < m;
   // rows beyond m convert to zero through the non-finite sentinel (their
   // outputs are never written)
-  const int32_t ea = rowok ? eA[arow] : kExpNonFinite;
+  const int32_t ea0 = rowok ? eA[arow] : kExpNonFinite;
+  const int32_t ea = ea0 == kExpNonFinite ? -2000 : ea0;   // see fuse_limbs
   const T* Ap = A + (rowok ? arow : 0);               // clamped: every load in bounds
   const int kq = (lane >> 4) * 16;                    // this lane's k bytes in a step
 
@@ -157,7 +176,7 @@ __global__ __launch_bounds__(256) void k234_fused(
     }
     Limbs<2> L[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) L[j] = make_limbs<2>(raw[j], ea);
+    for (int j = 0; j < 16; ++j) L[j] = fuse_limbs(raw[j], ea);
     const bool more = s + 1 < nsteps;
     if (more) {
       load_a(k0 + kFuseK, raw);

@@ -55,13 +55,20 @@ OZ2_HD int residue_odd(const Limbs<LIMBS>& L, const double* pw, double p, double
   return (int)fma(-q, p, y);
 }
 
-// a' = x_0 (mod 256) since 256 divides 2^40; x_0 (|x_0| < 2^40) does not fit
-// an int32, so its low byte is taken exactly in binary64.
+// a' = x_0 (mod 256) since 256 divides 2^40.  x_0 (|x_0| < 2^40) does not
+// fit an int32; x_0 + 1.5 2^52 is exact and lies in [2^52, 2^53), where the
+// integer significand is x_0 + 2^51 + 2^52, so the low 32 bits of its
+// encoding are x_0 modulo 2^32 in two's complement: the residue is their low
+// byte (the higher bits are not part of the result).
+template <int LIMBS>
+OZ2_HD uint32_t residue_256_byte(const Limbs<LIMBS>& L) {
+  return (uint32_t)f64_to_bits(L.x[0] + 0x1.8p52);
+}
+
+// The same residue as a signed value in [-128, 127].
 template <int LIMBS>
 OZ2_HD int residue_256(const Limbs<LIMBS>& L) {
-  const double x = L.x[0];
-  const double lo = fma(sconst(-256.0), floor(ldexp(x, -8)), x);   // in [0, 256), exact
-  return (int)(int8_t)(uint8_t)(int)lo;
+  return (int)(int8_t)(uint8_t)residue_256_byte<LIMBS>(L);
 }
 
 // Residues in plane t of EPT entries (limbs L), packed four to a dword in
@@ -73,8 +80,10 @@ __device__ __forceinline__ void pack_residues(const Limbs<LIMBS> (&L)[EPT], int 
   if (t == 0) {  // modulus 0 is 256
 #pragma unroll
     for (int q = 0; q < EPT / 4; ++q)
-      w[q] = pack_low_bytes(residue_256<LIMBS>(L[4 * q]), residue_256<LIMBS>(L[4 * q + 1]),
-                            residue_256<LIMBS>(L[4 * q + 2]), residue_256<LIMBS>(L[4 * q + 3]));
+      w[q] = pack_low_bytes(residue_256_byte<LIMBS>(L[4 * q]),
+                            residue_256_byte<LIMBS>(L[4 * q + 1]),
+                            residue_256_byte<LIMBS>(L[4 * q + 2]),
+                            residue_256_byte<LIMBS>(L[4 * q + 3]));
   } else {
     const double p = tab->p[t], ip = tab->inv_p[t];
     const double* pw = tab->powL[t];

@@ -10,11 +10,14 @@
 // Exact arithmetic in binary64: W_t is held as 39-bit slices w_ts, so each
 // slice sum |Acc_s| = |sum_t w_ts U_t| < 20 * 2^39 * 2^9 < 2^53 is exact.
 // The quotient Q = round(X / P) (|Q| < 2^14) is estimated from a rounded X; every
-// R_s = Acc_s - Q P_s is exact, carries are propagated exactly, and an exact
-// signed comparison with P/2 corrects a quotient that is off by one (skipped
-// when a rounded value of R already shows |R| < P/4).  The
-// magnitude is then rounded once, to nearest even, at the bit position that
-// the output format (binary64 or binary32, subnormals included) dictates.
+// R_s = Acc_s - Q P_s is exact, and an exact signed comparison with P/2
+// corrects a quotient that is off by one (skipped when a rounded value of R
+// already shows |R| < P/4).  That rounded value also gives the sign; the
+// magnitude's slices are normalised (carries propagated exactly) and rounded
+// once, to nearest even, at the bit position that the output format
+// (binary64 or binary32, subnormals included) dictates: for normal results by
+// one binary64 addition of two exact operands, otherwise by cutting the
+// slices at that bit.
 #pragma once
 
 #include "oz2_k1_norm.hpp"
@@ -44,26 +47,127 @@ OZ2_HD int sign_of(double (&D)[S]) {
   return 0;
 }
 
+// Rounded value of sum_s R_s 2^(39 s), by Horner steps (one rounding each).
+// For integer slices |R_s| < 2^53 - 2^39 the result is exact while
+// |sum| < 2^53: every partial sum is then an integer below 2^53.
+// Otherwise each step rounds a partial sum of magnitude at least 2^52
+// times its slice weight, so the relative error stays below S 2^-53 (1 + 2^-37)
+// < 2^-50: the result has the sign of the sum, is zero only for a zero sum,
+// and is within a factor 1 +- 2^-50 of it.
+template <int S>
+OZ2_HD double slices_value(const double (&R)[S]) {
+  double v = R[S - 1];
+#pragma unroll
+  for (int s = S - 2; s >= 0; --s) v = fma(v, sconst(0x1p39), R[s]);
+  return v;
+}
+
+// Correct rounding, to nearest even at the output format's quantum, of
+// V 2^-E for V = sum_s R_s 2^(39 s) > 0 with normalised slices (every R_s
+// in [0, 2^39)): the exponent of the leading bit, L = floor(log2 V), fixes
+// the quantum 2^q, q = max(L - (PREC - 1), E + EMIN_Q), and the slices are
+// cut at bit q.  Used for the outputs the direct form below does not cover
+// (subnormal results and zero).
+template <int S, int PREC, int EMIN_Q>
+OZ2_HD double round_slices_general(const double (&R)[S], int32_t E) {
+  int j = S - 1;
+  while (j > 0 && R[j] == 0.0) --j;
+  if (R[j] == 0.0) return 0.0;
+  double frac;
+  const int L = 39 * j + split_pow2(R[j], &frac);   // floor(log2 V)
+  const int q = (L - (PREC - 1)) > (E + EMIN_Q) ? (L - (PREC - 1)) : (E + EMIN_Q);
+  if (q <= 0) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = S - 1; s >= 0; --s) v += ldexp(R[s], 39 * s);  // exact: V < 2^PREC
+    return ldexp(v, -E);
+  }
+  if (q - 1 > L) return 0.0;                         // below half the quantum
+  const int sstar = (q - 1) / 39;                    // slice holding bit q-1
+  double Tq = 0.0, ftop = 0.0;
+  bool rest = false;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double vs = ldexp(R[s], 39 * s - q);             // exact
+    double I = floor(vs);
+    double f = vs - I;
+    Tq += I;
+    if (s == sstar) ftop = f;
+    else if (s < sstar && f != 0.0) rest = true;
+  }
+  const double cmp = ftop - 0.5;
+  const bool odd = floor(Tq * 0.5) * 2.0 != Tq;     // Tq < 2^53: an exact integer
+  const bool up = cmp > 0.0 || (cmp == 0.0 && (rest || odd));
+  return ldexp(Tq + (up ? 1.0 : 0.0), q - E);
+}
+
+// The same rounding in a few binary64 operations when the top slice R_{S-1}
+// is nonzero and the result is normal.  In units u = 2^(39 (S-2)),
+// V / u = t 2^39 + u1 + u2 2^-39 + z (t = R_{S-1}, u1 = R_{S-2},
+// u2 = R_{S-3}, z = the rest, 0 <= z < 2^-39), and the 53-bit rounding of
+// V / u is one binary64 addition X + Y of two exact operands:
+//  * t < 2^14: X = t 2^39 + u1 < 2^53 (exact), Y = u2 2^-39 plus 2^-40 when
+//    z > 0.  V / u >= 2^39, so every rounding boundary (half an ulp) is a
+//    multiple of 2^-14; V / u and X + Y lie on the same side of each such
+//    multiple of 2^-39 (both strictly between two of them when z > 0).
+//  * t >= 2^14: X = t 2^39, Y = u1 plus 1/2 when u2 or z is nonzero.
+//    V / u >= 2^53, so the boundaries are integers, and the same argument
+//    holds with integer spacing.
+// For binary32 the sum is rounded to odd at 53 bits (Y - (s - X) is the exact
+// error of s = X + Y, |X| >= |Y|): rounding that to 24 bits is the correct
+// rounding of V, since 53 >= 24 + 2.  Returns false (leaving out unset)
+// when the scaled result falls below the smallest normal number.
+template <int S, int PREC, int EMIN_Q>
+OZ2_HD bool round_slices_top(const double (&R)[S], int32_t E, double* out) {
+  double res;
+  int k;
+  if constexpr (S == 1) {
+    res = R[0];                                      // exact
+    k = -E;
+  } else {
+    const double t = R[S - 1], u1 = R[S - 2];
+    double u2 = 0.0;
+    if constexpr (S >= 3) u2 = R[S - 3];
+    bool z = false;
+#pragma unroll
+    for (int s = 0; s + 3 < S; ++s) z = z || R[s] != 0.0;
+    const bool small = t < 0x1p14;
+    const double X = small ? fma(t, sconst(0x1p39), u1) : t * 0x1p39;
+    const double Y = small ? fma(u2, sconst(0x1p-39), z ? 0x1p-40 : 0.0)
+                           : u1 + ((z || u2 != 0.0) ? 0.5 : 0.0);
+    res = X + Y;
+    if constexpr (PREC < 53) {
+      const double err = Y - (res - X);
+      if (err != 0.0) {
+        uint64_t b = f64_to_bits(res);
+        if (err < 0.0) b -= 1;
+        res = bits_to_f64(b | 1);
+      }
+    }
+    k = 39 * (S - 2) - E;
+  }
+  int ex;
+  (void)frexp(res, &ex);                             // res in [2^(ex-1), 2^ex)
+  if (ex - 1 + k < EMIN_Q + PREC - 1) return false;
+  *out = ldexp(res, k);
+  return true;
+}
+
 // PREC = 53 (binary64) or 24 (binary32); EMIN_Q = exponent of the smallest
 // subnormal (-1074 or -149).
 template <int S, int PREC, int EMIN_Q>
 OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) {
-  // Quotient estimate.
-  double xf = acc[S - 1];
-#pragma unroll
-  for (int s = S - 2; s >= 0; --s) xf = fma(xf, 0x1p39, acc[s]);
-  const double Q = rint(xf * T.invP);
+  // Quotient estimate and the exact residual R = X - Q P (|R_s| < 2^52:
+  // |Acc_s| < 2^51 and |Q P_s| < 2^51).
+  const double Q = rint(slices_value(acc) * T.invP);
   double R[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) R[s] = fma(-Q, T.P[s], acc[s]);
-  normalize(R);
   // Bring R into (-P/2, P/2): R = C'' + jP with |j| <= 1 and |C''| < P/2.
-  // Fast test first: the rounded value r of R is within 2^-52 |r| + 1 of R,
-  // so |r| <= quarterP (< P/4 (1 - 2^-30)) proves |R| < P/2, i.e. R = C''.
-  // Otherwise the exact comparisons with P/2 decide.
-  double r = R[S - 1];
-#pragma unroll
-  for (int s = S - 2; s >= 0; --s) r = fma(r, 0x1p39, R[s]);
+  // Fast test first: the rounded value r of R is within a factor 1 +- 2^-50
+  // of R, so |r| <= quarterP (< P/4 (1 - 2^-30)) proves |R| < P/2, i.e.
+  // R = C''.  Otherwise the exact comparisons with P/2 decide.
+  double r = slices_value(R);
   if (!(fabs(r) <= T.quarterP)) {
     double D[S];
 #pragma unroll
@@ -71,56 +175,35 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
     if (sign_of(D) > 0) {
 #pragma unroll
       for (int s = 0; s < S; ++s) R[s] -= T.P[s];
-      normalize(R);
     } else {
 #pragma unroll
       for (int s = 0; s < S; ++s) D[s] = R[s] + T.H[s];
       if (sign_of(D) < 0) {
 #pragma unroll
         for (int s = 0; s < S; ++s) R[s] += T.P[s];
-        normalize(R);
       }
     }
+    r = slices_value(R);
   }
-  // Sign and magnitude (all slices in [0, 2^39) after normalisation).
-  const bool neg = R[S - 1] < 0.0;
-  if (neg) {
+  // r has the sign of C'': the magnitude's slices, normalised into
+  // [0, 2^39) (all of them: the magnitude is non-negative).
+  const bool neg = r < 0.0;
+  const double sg = opaque_v(neg ? -1.0 : 1.0);
 #pragma unroll
-    for (int s = 0; s < S; ++s) R[s] = -R[s];
-    normalize(R);
+  for (int s = 0; s < S; ++s) R[s] *= sg;
+  normalize(R);
+  // Leading zero slices shifted out (V 2^-E = V' 2^-(E + 39 sh)).
+  int sh = 0;
+  while (sh < S - 1 && R[S - 1] == 0.0) {
+#pragma unroll
+    for (int s = S - 1; s > 0; --s) R[s] = R[s - 1];
+    R[0] = 0.0;
+    ++sh;
   }
-  int j = S - 1;
-  while (j > 0 && R[j] == 0.0) --j;
-  if (R[j] == 0.0) return 0.0;
-  double frac;
-  const int L = 39 * j + split_pow2(R[j], &frac);   // floor(log2 |C''|)
-  const int q = (L - (PREC - 1)) > (E + EMIN_Q) ? (L - (PREC - 1)) : (E + EMIN_Q);
+  const int32_t Es = E + 39 * sh;
   double res;
-  if (q <= 0) {
-    double v = 0.0;
-#pragma unroll
-    for (int s = S - 1; s >= 0; --s) v += ldexp(R[s], 39 * s);  // exact: |C''| < 2^PREC
-    res = ldexp(v, -E);
-  } else if (q - 1 > L) {
-    res = 0.0;                                       // below half the quantum
-  } else {
-    const int sstar = (q - 1) / 39;                  // slice holding bit q-1
-    double Tq = 0.0, ftop = 0.0;
-    bool rest = false;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      double vs = ldexp(R[s], 39 * s - q);           // exact
-      double I = floor(vs);
-      double f = vs - I;
-      Tq += I;
-      if (s == sstar) ftop = f;
-      else if (s < sstar && f != 0.0) rest = true;
-    }
-    const double cmp = ftop - 0.5;
-    const bool odd = floor(Tq * 0.5) * 2.0 != Tq;   // Tq < 2^53: an exact integer
-    const bool up = cmp > 0.0 || (cmp == 0.0 && (rest || odd));
-    res = ldexp(Tq + (up ? 1.0 : 0.0), q - E);
-  }
+  if (!(R[S - 1] != 0.0 && round_slices_top<S, PREC, EMIN_Q>(R, Es, &res)))
+    res = round_slices_general<S, PREC, EMIN_Q>(R, Es);
   return neg ? -res : res;
 }
 
@@ -156,8 +239,18 @@ __device__ __forceinline__ void k4_crt_body(
   const ModTable& T = *tab;
   // The plane bytes are loaded in groups of PF planes, the next group's
   // loads issued before the current group is accumulated, so a wave waits
-  // for memory once per group instead of once per plane.
+  // for memory once per group instead of once per plane.  The next group's
+  // plane indices are clamped to N - 1 (a repeated, in-bounds load) rather
+  // than skipped: with a fixed number of loads in flight the waits before
+  // the current group's accumulation leave the next group's loads pending.
   constexpr int R = 8, RW = 2, PF = 4;
+  // The row exponents of this lane's outputs, loaded up front.
+  int32_t er[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t row = bi * 32 + acc_row(R * h + r, lane);
+    er[r] = row < m ? eA[row] : 0;
+  }
   double acc[R][S];
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -181,12 +274,11 @@ __device__ __forceinline__ void k4_crt_body(
   };
   uint32_t cur[PF][RW] = {}, nxt[PF][RW] = {};
 #pragma unroll
-  for (int i = 0; i < PF; ++i)
-    if (i < N) load_plane(i, cur[i]);
+  for (int i = 0; i < PF; ++i) load_plane(i < N ? i : N - 1, cur[i]);
   for (int t0 = 0; t0 < N; t0 += PF) {
 #pragma unroll
     for (int i = 0; i < PF; ++i)
-      if (t0 + PF + i < N) load_plane(t0 + PF + i, nxt[i]);
+      load_plane(t0 + PF + i < N ? t0 + PF + i : N - 1, nxt[i]);
 #pragma unroll
     for (int i = 0; i < PF; ++i)
       if (t0 + i < N) accumulate(t0 + i, cur[i]);
@@ -201,7 +293,7 @@ __device__ __forceinline__ void k4_crt_body(
     const int64_t row = bi * 32 + lr;
     double v = 0.0;
     if (row < m && col < n) {
-      const int32_t e = eA[row];
+      const int32_t e = er[r];
       if (e == kExpNonFinite || f == kExpNonFinite) {
         v = __builtin_nan("");
       } else {

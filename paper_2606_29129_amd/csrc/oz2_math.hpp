@@ -29,6 +29,17 @@ OZ2_HD double sconst(double c) {
 #endif
 }
 
+// A value the compiler may not look through (it stays in its vector
+// registers unchanged).  A multiplier of +-1 is otherwise rewritten as a
+// select between x and -x: two 32-bit selects and a sign flip per binary64
+// operand instead of one multiply.
+OZ2_HD double opaque_v(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(x));
+#endif
+  return x;
+}
+
 // The low bytes of four 32-bit values in one dword (v0's in byte 0): two
 // byte permutes gather the pairs, a third joins them (three instructions;
 // masking and shifting each byte takes six).
