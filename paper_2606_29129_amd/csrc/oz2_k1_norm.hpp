@@ -65,11 +65,9 @@ __device__ __forceinline__ void k1_partials_strided_body(
 #pragma unroll
       for (int i = 0; i < 16; ++i)
         a[i] = norm_entry<RESC>((double)__builtin_nontemporal_load(p + (int64_t)(b + i) * ld));
+      s = ru_add_squares(s, a);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        s = ru_add(s, ru_square(a[i]));
-        mx = fmax(mx, fabs(a[i]));
-      }
+      for (int i = 0; i < 16; ++i) mx = fmax(mx, fabs(a[i]));
     }
   } else {
     for (int64_t h = 0; h < len; ++h) {
@@ -114,11 +112,9 @@ __device__ __forceinline__ void k1_partials_contig_body(
       double a[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = norm_entry<RESC>((double)p[b + i]);
+      s = ru_add_squares(s, a);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        s = ru_add(s, ru_square(a[i]));
-        mx = fmax(mx, fabs(a[i]));
-      }
+      for (int i = 0; i < 16; ++i) mx = fmax(mx, fabs(a[i]));
     }
   } else {
     for (int64_t h = 0; h < len; ++h) {

@@ -82,14 +82,21 @@ OZ2_HD float rd_f32(double d) {
   return f;
 }
 
-// RU(a*a) in binary64.  The FMA residual fma(a, a, -p) is exact when
-// a*a >= 2^-970; below that (|a| < 2^-480) the square is formed on a*2^600
-// and scaled back, rounding up once more (rounding up onto a coarser grid
-// after rounding up onto a finer one that contains it is one rounding up).
+// RU(x*x) for x = 0 or x >= 2^-480: the FMA residual fma(x, x, -p) is then
+// exact.  An infinite or NaN square passes through (its residual is not
+// positive).
+OZ2_HD double ru_square_normal(double x) {
+  const double p = x * x;
+  return fma(x, x, -p) > 0.0 ? next_up_nonneg(p) : p;
+}
+
+// RU(a*a) in binary64.  Below |a| = 2^-480 the residual would not be exact,
+// so the square is formed on a*2^600 and scaled back, rounding up once more
+// (rounding up onto a coarser grid after rounding up onto a finer one that
+// contains it is one rounding up).
 OZ2_HD double ru_square(double a) {
-  double x = a < 0 ? -a : a;
-  if (x < 0x1p-480) {
-    if (x == 0.0) return 0.0;
+  const double x = a < 0 ? -a : a;
+  if (x < 0x1p-480 && x != 0.0) {
     double b = ldexp(x, 600);              // exact, b < 2^120
     double pb = b * b;                     // >= 2^-948: residual exact
     double eb = fma(b, b, -pb);
@@ -98,19 +105,39 @@ OZ2_HD double ru_square(double a) {
     if (ldexp(r, 1200) < pb) r = next_up_nonneg(r);  // scaling back is exact
     return r;
   }
-  double p = x * x;
-  if (!(p <= 1.7976931348623157e308)) return p;  // inf (or NaN from a NaN)
-  double e = fma(x, x, -p);
-  return e > 0.0 ? next_up_nonneg(p) : p;
+  return ru_square_normal(x);
 }
 
-// RU(x + y) in binary64 for x, y >= 0 (Knuth's TwoSum gives the exact error).
+// RU(x + y) for x, y >= 0: the rounded sum, raised by one ulp when the exact
+// error (TwoSum) is positive.  An infinite or NaN sum passes through (its
+// error is NaN).
 OZ2_HD double ru_add(double x, double y) {
-  double s = x + y;
-  if (!(s <= 1.7976931348623157e308)) return s;
-  double bb = s - x;
-  double err = (x - (s - bb)) + (y - bb);
+  const double s = x + y;
+  const double bb = s - x;
+  const double err = (x - (s - bb)) + (y - bb);
   return err > 0.0 ? next_up_nonneg(s) : s;
+}
+
+// s + a_0^2 + ... + a_{NA-1}^2 with every square and every addition rounded
+// up, in that order.  The group is screened once for tiny entries
+// (0 < |a| < 2^-480, which take ru_square's scaled path); a group without
+// any runs as straight-line code.
+template <int NA>
+OZ2_HD double ru_add_squares(double s, const double (&a)[NA]) {
+  bool tiny = false;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const double x = a[i] < 0 ? -a[i] : a[i];
+    tiny = tiny || (x < 0x1p-480 && x != 0.0);
+  }
+  if (tiny) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) s = ru_add(s, ru_square(a[i]));
+  } else {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) s = ru_add(s, ru_square_normal(a[i] < 0 ? -a[i] : a[i]));
+  }
+  return s;
 }
 
 // floor(log2 x) of a finite x > 0 and the exact ratio x / 2^s in [1, 2).
