@@ -335,8 +335,9 @@ def batched_leg(steps, warmup, target=1e-15, count=256, seed=0, check=4):
     stream = torch.cuda.current_stream()
     _, Ns = oz.dgemm_batched(pairs, 0, target=target, return_N=True)
     torch.cuda.synchronize()
-    py_Ns = [autotune.pick_N(A.shape[1], max(autotune.estimate_phi(A), autotune.estimate_phi(B)),
-                             target) for A, B in pairs]
+    py_Ns = [autotune.pick_N(A.shape[1], max(autotune.estimate_phi(A, "rows"),
+                                             autotune.estimate_phi(B, "cols")), target)
+             for A, B in pairs]
     # fixed outputs: every replay writes the same matrices (no pointer refresh)
     outs = [torch.empty((A.shape[0], B.shape[1]), dtype=torch.float64, device=dev)
             for A, B in pairs]
@@ -589,7 +590,8 @@ def main():
     # N for the error target: the library's autotuner on phi estimated from
     # the operands (the larger of the two estimates)
     oz.ensure_workspace(1024)
-    phi_hat = max(oz.ozaki2_estimate_phi(m, k, A_cm, m), oz.ozaki2_estimate_phi(k, n, B_cm, k))
+    phi_hat = max(oz.ozaki2_estimate_phi(m, k, A_cm, m, 0),    # the rows of A
+                  oz.ozaki2_estimate_phi(k, n, B_cm, k, 1))    # the columns of B
     N_tuned = oz.ozaki2_autotune_N(k, phi_hat, args.target)
     N = args.N or N_tuned
     Ns_used = {N} | (set() if args.no_n14 else {14})

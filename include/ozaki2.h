@@ -346,7 +346,8 @@ typedef struct oz2_problem {
  * Problems with N = 0 get the smallest N whose calibrated maximum relative
  * error (the library's autotuner, see ozaki2_autotune_N) is at most
  * target_max_rel_err / 4 for their k and for phi estimated from their data
- * (ozaki2_estimate_phi of A and of B, the larger of the two); this reads the
+ * (ozaki2_estimate_phi of the rows of A and of the columns of B, the larger
+ * of the two); this reads the
  * operands once more and synchronises the stream before the launch.  The
  * target is ignored when every N is given.
  *
@@ -407,16 +408,22 @@ int ozaki2_dgemm_batched_workspace_size(int batch, const oz2_problem* problems, 
  * in (0, 1]; -4 N is NULL.
  *
  * ozaki2_estimate_phi -- phi of a column-major rows x cols binary64 device
- * matrix (leading dimension ld): sqrt(max(var - 1, 0)) with var the unbiased
- * sample variance of log|x| over its first min(rows cols, 2^20) entries in
- * storage order, zeros and non-finite entries skipped (0 with fewer than two
- * such entries).  Uses the first KiB of the workspace (same
- * workspace rules as ozaki2_dgemm) and synchronises the stream.  Returns 0;
- * -1..-5 for the argument in that position; OZ2_ERR_WORKSPACE; or
- * OZ2_ERR_HIP.
+ * matrix (leading dimension ld) whose vectors -- the units the scaling
+ * treats -- are its rows (vectors = 0, as for A) or its columns (vectors =
+ * 1, as for B): sqrt(max(var - 1, 0)) with var the variance of log|x| within
+ * the vectors, pooled over them (the sum over vectors of the squared
+ * deviations from the vector's mean, over the sum of (count - 1)), on a
+ * sample of about 2^20 entries: every vector with its first
+ * max(2, 2^20 / (number of vectors)) entries; zeros and non-finite entries
+ * are skipped and
+ * a vector with fewer than two entries left out (0 when none has two).
+ * Scaling rows (columns) by different powers of two leaves it unchanged.
+ * Uses the first KiB of the workspace (same workspace rules as ozaki2_dgemm)
+ * and synchronises the stream.  Returns 0; -1..-6 for the argument in that
+ * position; OZ2_ERR_WORKSPACE; or OZ2_ERR_HIP.
  */
 int ozaki2_autotune_N(int64_t k, double phi, double target_max_rel_err, int* N);
-int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld,
+int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld, int vectors,
                         double* phi);
 
 /*

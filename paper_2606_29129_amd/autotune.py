@@ -12,7 +12,7 @@ paper's experiments, (rand - 0.5) exp(phi randn), is controlled by phi
 * picks, for a problem, the smallest N whose calibrated error at the next
   larger grid point in k and phi is below the target (``pick_N``), with phi
   estimated from the data: for this distribution log|a| has variance
-  1 + phi^2 (``estimate_phi``).
+  1 + phi^2 (``estimate_phi``: pooled within the rows of A and the columns of B).
 
 The exact reference is computed here with Python integers (every binary64
 value is an integer times a power of two).
@@ -73,21 +73,42 @@ def rel_err(c: float, ref) -> float:
     return abs(diff) / abs(n << (e - lo))
 
 
-def estimate_phi(A) -> float:
-    """phi of (rand-0.5) exp(phi randn) from a tensor or array of samples."""
+def estimate_phi(X, vectors: str = "rows") -> float:
+    """phi of (rand-0.5) exp(phi randn) from a matrix (numpy array or torch
+    tensor, the logical rows x cols matrix): sqrt(max(var - 1, 0)) with var
+    the variance of log|x| within the vectors the scaling treats -- its rows
+    (``vectors="rows"``, as for A) or its columns (``"cols"``, as for B) --
+    pooled over the vectors, on the sample ozaki2_estimate_phi uses (every
+    vector with its first max(2, 2^20 / (number of vectors)) entries); zeros
+    and non-finite entries skipped, vectors with fewer than two entries left
+    out (0 when none has two).  Rows or columns scaled by different powers
+    of two leave it unchanged, as they leave the revised scaling's bits."""
+    if vectors not in ("rows", "cols"):
+        raise ValueError(vectors)
+    rows, cols = X.shape
+    nvec, full = (rows, cols) if vectors == "rows" else (cols, rows)
+    L = min(full, max(2, (1 << 20) // max(nvec, 1)))
+    S = X[:, :L] if vectors == "rows" else X[:L, :]
     try:
         import torch
-        if isinstance(A, torch.Tensor):
-            x = A.reshape(-1)[: 1 << 20]
-            x = x[x != 0].abs().log()
-            v = float(x.var()) if x.numel() > 1 else 1.0
-            return math.sqrt(max(v - 1.0, 0.0))
+        if isinstance(S, torch.Tensor):
+            S = S.detach().cpu().numpy()
     except ImportError:
         pass
-    x = np.asarray(A, np.float64).ravel()[: 1 << 20]
-    x = np.log(np.abs(x[x != 0]))
-    v = float(x.var()) if x.size > 1 else 1.0
-    return math.sqrt(max(v - 1.0, 0.0))
+    S = np.asarray(S, np.float64)
+    if vectors == "cols":
+        S = S.T
+    ok = (S != 0) & np.isfinite(S)
+    lg = np.where(ok, np.log(np.where(ok, np.abs(S), 1.0)), 0.0)
+    n = ok.sum(axis=1)
+    mean = lg.sum(axis=1) / np.maximum(n, 1)
+    dev = np.where(ok, lg - mean[:, None], 0.0)
+    use = n >= 2
+    D = float((n[use] - 1).sum())
+    if D <= 0:
+        return 0.0
+    var = float((dev[use] ** 2).sum()) / D
+    return math.sqrt(max(var - 1.0, 0.0))
 
 
 _table_cache = None

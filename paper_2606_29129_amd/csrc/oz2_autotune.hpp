@@ -4,10 +4,14 @@
 // the scaled integers keep (more moduli: larger P, wider integers) and by the
 // spread of the entry magnitudes.  For the distribution of the paper's
 // experiments, (rand - 0.5) exp(phi randn) (Section 3.2), log|a| has variance
-// 1 + phi^2, so phi is estimated from the sample variance of log|a| over the
-// first 2^20 entries of each operand (storage order; zeros and non-finite
-// entries skipped), and N is the smallest number of moduli whose error
-// estimate is at most target / kTuneMargin.  The estimate is an upper
+// 1 + phi^2, so phi is estimated from the variance of log|a| within the
+// vectors the scaling treats -- the rows of A, the columns of B -- pooled
+// over a sample of about 2^20 entries of each operand (zeros and non-finite
+// entries skipped): the spread of magnitudes inside a vector is what its
+// scale exponent cannot absorb, so, like the revised scaling itself, the
+// estimate does not change when rows or columns are scaled by different
+// powers of two.  N is the smallest number of moduli whose error estimate is
+// at most target / kTuneMargin.  The estimate is an upper
 // envelope of the calibrated maxima (oz2_autotune_table.hpp), so that the
 // pick never falls when k, phi or the accuracy demand grows even where the
 // single-seed measurements are not monotone: at each grid point the largest
@@ -87,62 +91,151 @@ inline int tune_pick_N(int64_t k, double phi, double target) {
   return kTuneN0 + kTuneNN - 1;
 }
 
-// One operand whose log-magnitude statistics are wanted.
+// The sample of one operand whose log-magnitude spread is wanted: nvec
+// vectors -- the rows of A or the columns of B, the vectors the scaling
+// treats one by one -- of len entries each; entry e of vector v at
+// X[v vstride + e estride].
 struct StatSrc {
   const double* X;
-  int64_t rows, ld, count;   // column-major rows x (count / rows ...), count <= 2^20
+  int64_t nvec, len, vstride, estride;
 };
 
-// Per-block partial statistics (number, sum and sum of squares of log|x|)
-// of the first `count` entries in storage order (entry g at row g % rows,
-// column g / rows).  Block b covers operand b / kStatBlocks; the host adds
-// the partials of an operand in block order (deterministic).
+typedef __attribute__((address_space(1))) const double GlobalDouble;
+
+// Count, sum and sum of squares of log|x| - x0 over the entries e0, e0 +
+// step, ... below e1 of vector v (zeros and non-finite entries skipped), x0
+// being log|x| of the vector's first entry when that is finite and nonzero,
+// else 0 (the shift keeps the variance free of cancellation when the
+// vector's magnitudes sit far from 1).  Four entries per round, their loads
+// issued together.
+__device__ __forceinline__ void vec_logsums(GlobalDouble* X, const StatSrc& s, int64_t v,
+                                            int64_t e0, int64_t e1, int64_t step, double* n,
+                                            double* s1, double* s2) {
+  GlobalDouble* x = X + v * s.vstride;
+  const double f = fabs(x[0]);
+  const double x0 = (f > 0.0 && f <= 1.7976931348623157e308) ? log(f) : 0.0;
+  double c = 0.0, a = 0.0, q = 0.0;
+  auto add = [&](double y) {
+    y = fabs(y);
+    if (y > 0.0 && y <= 1.7976931348623157e308) {
+      const double d = log(y) - x0;
+      c += 1.0;
+      a += d;
+      q += d * d;
+    }
+  };
+  int64_t e = e0;
+  for (; e + 3 * step < e1; e += 4 * step) {
+    double y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) y[i] = x[(e + i * step) * s.estride];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) add(y[i]);
+  }
+  for (; e < e1; e += step) add(x[e * s.estride]);
+  *n = c;
+  *s1 = a;
+  *s2 = q;
+}
+
+// Per-block partial sums of the pooled within-vector statistics of one
+// operand: W = sum over vectors of sum (log|x| - mean of the vector)^2 and
+// D = sum over vectors of (count - 1), vectors with fewer than two entries
+// left out.  Block b covers operand b / kStatBlocks; the host adds the
+// partials of an operand in block order (deterministic).  Strided vectors
+// (rows of a column-major matrix): 64 consecutive vectors per pass of a
+// block, one per lane so that a load reads neighbouring vectors, the four
+// waves taking four consecutive ranges of the entries, their sums of a
+// vector added in wave order.  Contiguous vectors (columns): one wave per
+// vector, its lanes reading neighbouring entries, the lanes' sums combined
+// across the wave.
 __global__ __launch_bounds__(256) void k_logstats(const StatSrc* __restrict__ src,
                                                   double* __restrict__ part) {
-  __shared__ double red[3][256];
+  __shared__ double red[2][256];
+  __shared__ double ws[3][4][64];
   const int op = blockIdx.x / kStatBlocks, sub = blockIdx.x % kStatBlocks;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const StatSrc s = src[op];
   // The operand pointer comes from a descriptor, so the compiler cannot tell
   // it is global memory; read through a global pointer (generic loads would
   // be flat accesses, each waited for before the next use).
-  typedef __attribute__((address_space(1))) const double GlobalDouble;
   GlobalDouble* X = (GlobalDouble*)s.X;
-  double c = 0.0, sum = 0.0, sq = 0.0;
-  for (int64_t g = (int64_t)sub * 256 + threadIdx.x; g < s.count;
-       g += (int64_t)kStatBlocks * 256) {
-    const int64_t i = g % s.rows, h = g / s.rows;
-    const double x = fabs(X[i + h * s.ld]);
-    if (x > 0.0 && x <= 1.7976931348623157e308) {
-      const double l = log(x);
-      c += 1.0;
-      sum += l;
-      sq += l * l;
+  double W = 0.0, D = 0.0;
+  if (s.estride != 1) {
+    const int64_t q = (s.len + 3) / 4;
+    const int64_t e0 = wave * q, e1 = e0 + q < s.len ? e0 + q : s.len;
+    for (int64_t g = sub; g * 64 < s.nvec; g += kStatBlocks) {
+      const int64_t v = g * 64 + lane;
+      double n = 0.0, s1 = 0.0, s2 = 0.0;
+      if (v < s.nvec) vec_logsums(X, s, v, e0, e1, 1, &n, &s1, &s2);
+      ws[0][wave][lane] = n;
+      ws[1][wave][lane] = s1;
+      ws[2][wave][lane] = s2;
+      __syncthreads();
+      if (wave == 0 && v < s.nvec) {
+        double t[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          t[k] = ((ws[k][0][lane] + ws[k][1][lane]) + ws[k][2][lane]) + ws[k][3][lane];
+        if (t[0] >= 2.0) {
+          W += t[2] - t[1] * t[1] / t[0];
+          D += t[0] - 1.0;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int64_t v = (int64_t)sub * 4 + wave; v < s.nvec; v += (int64_t)kStatBlocks * 4) {
+      double n, s1, s2;
+      vec_logsums(X, s, v, lane, s.len, 64, &n, &s1, &s2);
+      for (int o = 32; o > 0; o >>= 1) {
+        n += __shfl_xor(n, o);
+        s1 += __shfl_xor(s1, o);
+        s2 += __shfl_xor(s2, o);
+      }
+      if (lane == 0 && n >= 2.0) {
+        W += s2 - s1 * s1 / n;
+        D += n - 1.0;
+      }
     }
   }
-  red[0][threadIdx.x] = c;
-  red[1][threadIdx.x] = sum;
-  red[2][threadIdx.x] = sq;
+  red[0][tid] = W;
+  red[1][tid] = D;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x < 3) part[((int64_t)op * kStatBlocks + sub) * 3 + threadIdx.x] = red[threadIdx.x][0];
+  if (tid < 2) part[((int64_t)op * kStatBlocks + sub) * 2 + tid] = red[tid][0];
 }
 
-// phi from the partials of one operand: sqrt(max(var(log|x|) - 1, 0)) with
-// the unbiased sample variance; fewer than two entries give 0.
+// phi from the partials of one operand: sqrt(max(var - 1, 0)) with var =
+// W / D the pooled within-vector sample variance of log|x|; 0 when no vector
+// has two entries.
 inline double phi_from_partials(const double* p) {
-  double c = 0.0, sum = 0.0, sq = 0.0;
+  double W = 0.0, D = 0.0;
   for (int b = 0; b < kStatBlocks; ++b) {
-    c += p[3 * b];
-    sum += p[3 * b + 1];
-    sq += p[3 * b + 2];
+    W += p[2 * b];
+    D += p[2 * b + 1];
   }
-  if (c < 2.0) return 0.0;
-  const double var = (sq - sum * sum / c) / (c - 1.0);
+  if (!(D > 0.0)) return 0.0;
+  const double var = W / D;
   return var > 1.0 ? sqrt(var - 1.0) : 0.0;
+}
+
+// The sample of a column-major rows x cols matrix (leading dimension ld)
+// whose vectors are its rows (by_cols = 0: A) or its columns (by_cols = 1:
+// B): every vector with its first max(2, kPhiSample / (number of vectors))
+// entries (all of them when it is shorter), about kPhiSample entries in all.
+inline StatSrc stat_src(const double* X, int64_t rows, int64_t cols, int64_t ld, int by_cols) {
+  const int64_t nvec = by_cols ? cols : rows, full = by_cols ? rows : cols;
+  int64_t len = kPhiSample / (nvec > 0 ? nvec : 1);
+  len = len < 2 ? 2 : len;
+  len = len < full ? len : full;
+  return by_cols ? StatSrc{X, nvec, len, ld, 1} : StatSrc{X, nvec, len, 1, ld};
 }
 
 }  // namespace oz2

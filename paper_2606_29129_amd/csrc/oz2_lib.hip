@@ -709,10 +709,11 @@ void batch_release() {
 // statistics) for `ns` operands; it sits right after the status word of the
 // workspace.
 size_t tune_scratch_bytes(size_t ns) {
-  return align256(sizeof(StatSrc) * ns) + align256(sizeof(double) * 3 * kStatBlocks * ns);
+  return align256(sizeof(StatSrc) * ns) + align256(sizeof(double) * 2 * kStatBlocks * ns);
 }
 
-// phi of each operand (sample variance of log|x|, oz2_autotune.hpp): one
+// phi of each operand (pooled within-vector variance of log|x|,
+// oz2_autotune.hpp): one
 // launch for all of them on the library stream into the workspace scratch
 // at `scratch`, then a synchronising copy of the per-block partials.
 int estimate_phis(char* scratch, const std::vector<StatSrc>& srcs, std::vector<double>* phis) {
@@ -720,7 +721,7 @@ int estimate_phis(char* scratch, const std::vector<StatSrc>& srcs, std::vector<d
   phis->assign(ns, 0.0);
   if (ns == 0) return 0;
   const size_t off_part = align256(sizeof(StatSrc) * ns);
-  std::vector<double> part(3 * kStatBlocks * ns);
+  std::vector<double> part(2 * kStatBlocks * ns);
   if (hipMemcpyAsync(scratch, srcs.data(), sizeof(StatSrc) * ns, hipMemcpyHostToDevice,
                      g_stream) != hipSuccess)
     return OZ2_ERR_HIP;
@@ -731,12 +732,8 @@ int estimate_phis(char* scratch, const std::vector<StatSrc>& srcs, std::vector<d
                      hipMemcpyDeviceToHost, g_stream) != hipSuccess ||
       hipStreamSynchronize(g_stream) != hipSuccess)
     return OZ2_ERR_HIP;
-  for (size_t i = 0; i < ns; ++i) (*phis)[i] = phi_from_partials(part.data() + 3 * kStatBlocks * i);
+  for (size_t i = 0; i < ns; ++i) (*phis)[i] = phi_from_partials(part.data() + 2 * kStatBlocks * i);
   return 0;
-}
-
-StatSrc stat_src(const double* X, int64_t rows, int64_t cols, int64_t ld) {
-  return StatSrc{X, rows > 0 ? rows : 1, ld, std::min<int64_t>(rows * cols, kPhiSample)};
 }
 
 // Everything a batch needs, planned on the host: the problems that run (m, n,
@@ -1124,8 +1121,8 @@ int ozaki2_dgemm_batched(int batch, oz2_problem* problems, int mode, double targ
     for (int i = 0; i < batch; ++i) {
       const oz2_problem& q = problems[i];
       if (q.N != 0 || q.m == 0 || q.n == 0 || q.k == 0) continue;
-      srcs.push_back(stat_src(q.A, q.m, q.k, q.lda));
-      srcs.push_back(stat_src(q.B, q.k, q.n, q.ldb));
+      srcs.push_back(stat_src(q.A, q.m, q.k, q.lda, 0));   // the rows of A
+      srcs.push_back(stat_src(q.B, q.k, q.n, q.ldb, 1));   // the columns of B
       who.push_back(i);
     }
     int dev;
@@ -1170,12 +1167,14 @@ int ozaki2_autotune_N(int64_t k, double phi, double target_max_rel_err, int* N) 
   return 0;
 }
 
-int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld, double* phi) {
+int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld, int vectors,
+                        double* phi) {
   if (rows < 0) return -1;
   if (cols < 0) return -2;
   if (!X && rows > 0 && cols > 0) return -3;
   if (ld < (rows > 1 ? rows : 1)) return -4;
-  if (!phi) return -5;
+  if (vectors != 0 && vectors != 1) return -5;
+  if (!phi) return -6;
   *phi = 0.0;
   if (rows == 0 || cols == 0) return 0;
   int dev, rc;
@@ -1183,7 +1182,7 @@ int ozaki2_estimate_phi(int64_t rows, int64_t cols, const double* X, int64_t ld,
   char* ws = nullptr;
   if ((rc = get_workspace(dev, 256 + tune_scratch_bytes(1), &ws))) return rc;
   std::vector<double> phis;
-  if ((rc = estimate_phis(ws + 256, {stat_src(X, rows, cols, ld)}, &phis))) return rc;
+  if ((rc = estimate_phis(ws + 256, {stat_src(X, rows, cols, ld, vectors)}, &phis))) return rc;
   *phi = phis[0];
   return 0;
 }

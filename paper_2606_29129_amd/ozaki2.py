@@ -66,7 +66,8 @@ _SIGS = {
     "ozaki2_dgemm_batched_workspace_size": ([_c_int, ctypes.POINTER(Oz2Problem), _c_int,
                                              ctypes.POINTER(ctypes.c_size_t)], _c_int),
     "ozaki2_autotune_N": ([_c_i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_c_int)], _c_int),
-    "ozaki2_estimate_phi": ([_c_i64, _c_i64, _vp, _c_i64, ctypes.POINTER(ctypes.c_double)], _c_int),
+    "ozaki2_estimate_phi": ([_c_i64, _c_i64, _vp, _c_i64, _c_int, ctypes.POINTER(ctypes.c_double)],
+                            _c_int),
 }
 
 
@@ -258,9 +259,9 @@ def ozaki2_autotune_N(k, phi, target):
     return N.value
 
 
-def ozaki2_estimate_phi(rows, cols, X, ld):
+def ozaki2_estimate_phi(rows, cols, X, ld, vectors):
     phi = ctypes.c_double(0.0)
-    _check("ozaki2_estimate_phi", lib().ozaki2_estimate_phi(rows, cols, _ptr(X), ld,
+    _check("ozaki2_estimate_phi", lib().ozaki2_estimate_phi(rows, cols, _ptr(X), ld, vectors,
                                                               ctypes.byref(phi)))
     return phi.value
 

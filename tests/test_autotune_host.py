@@ -13,7 +13,46 @@ from paper_2606_29129_amd import autotune, inputs
 @pytest.mark.parametrize("phi", [0.5, 1.0, 2.0, 3.0])
 def test_estimate_phi_recovers_the_generator_spread(phi):
     A = inputs.ozaki_matrix(200, 2000, phi, seed=5)
-    assert abs(autotune.estimate_phi(A) - phi) < 0.08 * max(1.0, phi)
+    assert abs(autotune.estimate_phi(A, "rows") - phi) < 0.08 * max(1.0, phi)
+    assert abs(autotune.estimate_phi(A, "cols") - phi) < 0.08 * max(1.0, phi)
+
+
+def _pooled_phi(vectors):
+    """The estimator's definition, one vector at a time."""
+    W = D = 0.0
+    for v in vectors:
+        v = np.asarray(v, np.float64)
+        x = np.log(np.abs(v[(v != 0) & np.isfinite(v)]))
+        if x.size >= 2:
+            W += float(((x - x.mean()) ** 2).sum())
+            D += x.size - 1
+    return math.sqrt(max(W / D - 1.0, 0.0)) if D > 0 else 0.0
+
+
+def test_estimate_phi_is_the_pooled_within_vector_spread_and_ignores_vector_scales():
+    """Against the definition written out vector by vector (with zeros,
+    infinities and a vector of one entry), on both orientations and the
+    sample sizes of the rule; scaling each row (column) by its own power of
+    two leaves it unchanged, while the variance of all entries taken
+    together grows."""
+    rng = np.random.default_rng(11)
+    X = inputs.ozaki_matrix(300, 40, 1.5, seed=2)
+    X[5, :] = 0.0
+    X[7, 3] = np.inf
+    X[9, 1:] = 0.0
+    assert abs(autotune.estimate_phi(X, "rows") - _pooled_phi(X)) < 1e-12
+    assert abs(autotune.estimate_phi(X, "cols") - _pooled_phi(X.T)) < 1e-12
+    big = inputs.ozaki_matrix(4096, 600, 0.7, seed=3)       # rows keep 256 entries each
+    assert abs(autotune.estimate_phi(big, "rows") - _pooled_phi(big[:, :256])) < 1e-12
+    assert abs(autotune.estimate_phi(big.T, "cols") - _pooled_phi(big[:, :256])) < 1e-12
+    wide = inputs.ozaki_matrix(400, 5000, 0.7, seed=4)      # columns keep 209 entries each
+    assert abs(autotune.estimate_phi(wide, "cols") - _pooled_phi(wide[:209, :].T)) < 1e-12
+    rs = np.ldexp(1.0, rng.integers(-300, 300, X.shape[0]))[:, None]
+    cs = np.ldexp(1.0, rng.integers(-300, 300, X.shape[1]))[None, :]
+    assert abs(autotune.estimate_phi(X * rs, "rows") - autotune.estimate_phi(X, "rows")) < 1e-9
+    assert abs(autotune.estimate_phi(X * cs, "cols") - autotune.estimate_phi(X, "cols")) < 1e-9
+    flat = np.log(np.abs((X * rs)[(X != 0) & np.isfinite(X)]))
+    assert math.sqrt(max(flat.var() - 1.0, 0.0)) > 10 * autotune.estimate_phi(X, "rows")
 
 
 def test_exact_dot_and_rel_err():
@@ -91,10 +130,13 @@ def test_autotune_argument_errors():
     assert lib.ozaki2_autotune_N(10, 1.0, 0.0, ctypes.byref(N)) == -3
     assert lib.ozaki2_autotune_N(10, 1.0, 1e-15, None) == -4
     phi = ctypes.c_double(0)
-    assert lib.ozaki2_estimate_phi(-1, 1, None, 1, ctypes.byref(phi)) == -1
-    assert lib.ozaki2_estimate_phi(4, 4, None, 4, ctypes.byref(phi)) == -3
-    assert lib.ozaki2_estimate_phi(4, 4, 8, 3, ctypes.byref(phi)) == -4
-    assert lib.ozaki2_estimate_phi(0, 4, None, 1, ctypes.byref(phi)) == 0 and phi.value == 0.0
+    assert lib.ozaki2_estimate_phi(-1, 1, None, 1, 0, ctypes.byref(phi)) == -1
+    assert lib.ozaki2_estimate_phi(4, -1, None, 4, 0, ctypes.byref(phi)) == -2
+    assert lib.ozaki2_estimate_phi(4, 4, None, 4, 0, ctypes.byref(phi)) == -3
+    assert lib.ozaki2_estimate_phi(4, 4, 8, 3, 0, ctypes.byref(phi)) == -4
+    assert lib.ozaki2_estimate_phi(4, 4, 8, 4, 2, ctypes.byref(phi)) == -5
+    assert lib.ozaki2_estimate_phi(4, 4, 8, 4, 1, None) == -6
+    assert lib.ozaki2_estimate_phi(0, 4, None, 1, 1, ctypes.byref(phi)) == 0 and phi.value == 0.0
     # a batch with N = 0 needs a target; nothing is launched
     prob = oz.Oz2Problem(4, 4, 4, 8, 4, 8, 4, 8, 4, 0, 0)
     arr = (oz.Oz2Problem * 1)(prob)

@@ -155,31 +155,50 @@ def test_batched_nonfinite_row_sets_status_and_nan_row():
             assert np.array_equal(_bits(C), _bits(C0))
 
 
-def _phi_ref(x):
-    """The estimator the library documents, in numpy: unbiased variance of
-    log|x| over the first 2^20 nonzero finite entries in storage order."""
-    x = np.asarray(x, np.float64).ravel()[: 1 << 20]
-    x = np.abs(x[(x != 0) & np.isfinite(x)])
-    if x.size < 2:
-        return 0.0
-    v = float(np.log(x).var(ddof=1))
-    return float(np.sqrt(max(v - 1.0, 0.0)))
+def _phi_ref(X, vectors):
+    """The estimator the library documents, one vector at a time in numpy:
+    the rows (or columns) of X, each with its first max(2, 2^20 / count)
+    entries; variance of log|x| within each vector pooled over them (zeros
+    and non-finite entries skipped, vectors with fewer than two left out)."""
+    X = np.asarray(X, np.float64)
+    vecs = X if vectors == 0 else X.T
+    L = min(vecs.shape[1], max(2, (1 << 20) // max(vecs.shape[0], 1)))
+    W = D = 0.0
+    for v in vecs[:, :L]:
+        x = np.log(np.abs(v[(v != 0) & np.isfinite(v)]))
+        if x.size >= 2:
+            W += float(((x - x.mean()) ** 2).sum())
+            D += x.size - 1
+    return float(np.sqrt(max(W / D - 1.0, 0.0))) if D > 0 else 0.0
 
 
 @pytest.mark.parametrize("rows,cols,ld,phi", [(300, 200, 300, 0.5), (1000, 1500, 1003, 2.7),
-                                              (4, 5, 9, 1.0), (2048, 1024, 2048, 4.0)])
-def test_estimate_phi_matches_numpy(rows, cols, ld, phi):
+                                              (4, 5, 9, 1.0), (2048, 1024, 2048, 4.0),
+                                              (20000, 64, 20000, 1.5)])
+@pytest.mark.parametrize("vectors", [0, 1])
+def test_estimate_phi_matches_numpy(rows, cols, ld, phi, vectors):
     X = inputs.ozaki_matrix(rows, cols, phi, seed=rows)
     if rows > 10:
-        X[::7] = 0.0                      # zero rows are skipped
+        X[::7] = 0.0                      # zero rows (and zero entries of columns) skipped
+        X[3, 2] = np.inf
     buf = np.zeros((cols, ld))            # column-major with leading dimension ld
     buf[:, :rows] = X.T
     oz.ensure_workspace(1024)              # the estimate's scratch
-    got = oz.ozaki2_estimate_phi(rows, cols, torch.from_numpy(buf).to(DEV), ld)
-    want = _phi_ref(X.T.ravel())          # storage order: column by column
+    dX = torch.from_numpy(buf).to(DEV)
+    got = oz.ozaki2_estimate_phi(rows, cols, dX, ld, vectors)
+    want = _phi_ref(X, vectors)
     assert abs(got - want) <= 1e-9 * max(1.0, want)
     if rows * cols > 5000:
         assert abs(got - phi) < 0.1      # and it estimates the distribution's phi
+    # rows (columns) scaled by their own powers of two: the same estimate
+    rng = np.random.default_rng(rows + vectors)
+    if vectors == 0:
+        Y = X * np.ldexp(1.0, rng.integers(-200, 200, rows))[:, None]
+    else:
+        Y = X * np.ldexp(1.0, rng.integers(-200, 200, cols))[None, :]
+    buf[:, :rows] = Y.T
+    got2 = oz.ozaki2_estimate_phi(rows, cols, torch.from_numpy(buf).to(DEV), ld, vectors)
+    assert abs(got2 - got) <= 1e-9 * max(1.0, got)
 
 
 def test_batched_autotune_picks_the_python_N_and_same_bits():
@@ -194,7 +213,7 @@ def test_batched_autotune_picks_the_python_N_and_same_bits():
         phi = float(rng.uniform(0.5, 3.0))
         A, B = inputs.problem(m, n, k, phi, seed=500 + i)
         pairs.append((torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)))
-        ph = max(_phi_ref(A), _phi_ref(B))
+        ph = max(_phi_ref(A, 0), _phi_ref(B, 1))      # the rows of A, the columns of B
         want.append(autotune.pick_N(k, ph, 1e-15))
     outs, used = oz.dgemm_batched(pairs, 0, target=1e-15, return_N=True)
     assert used == want
