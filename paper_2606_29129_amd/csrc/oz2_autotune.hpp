@@ -143,16 +143,18 @@ __device__ __forceinline__ void vec_logsums(GlobalDouble* X, const StatSrc& s, i
 // D = sum over vectors of (count - 1), vectors with fewer than two entries
 // left out.  Block b covers operand b / kStatBlocks; the host adds the
 // partials of an operand in block order (deterministic).  Strided vectors
-// (rows of a column-major matrix): 64 consecutive vectors per pass of a
-// block, one per lane so that a load reads neighbouring vectors, the four
-// waves taking four consecutive ranges of the entries, their sums of a
-// vector added in wave order.  Contiguous vectors (columns): one wave per
+// (rows of a column-major matrix): kStatRows consecutive vectors per pass of
+// a block, the block's threads split into kStatSegs groups that take
+// consecutive ranges of the entries (a load of a wave reads kStatRows
+// neighbouring vectors in each of its groups' columns), the groups' sums of
+// a vector added in group order.  Contiguous vectors (columns): one wave per
 // vector, its lanes reading neighbouring entries, the lanes' sums combined
 // across the wave.
+constexpr int kStatSegs = 16, kStatRows = 256 / kStatSegs;
 __global__ __launch_bounds__(256) void k_logstats(const StatSrc* __restrict__ src,
                                                   double* __restrict__ part) {
   __shared__ double red[2][256];
-  __shared__ double ws[3][4][64];
+  __shared__ double ws[3][kStatSegs][kStatRows];
   const int op = blockIdx.x / kStatBlocks, sub = blockIdx.x % kStatBlocks;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const StatSrc s = src[op];
@@ -162,21 +164,22 @@ __global__ __launch_bounds__(256) void k_logstats(const StatSrc* __restrict__ sr
   GlobalDouble* X = (GlobalDouble*)s.X;
   double W = 0.0, D = 0.0;
   if (s.estride != 1) {
-    const int64_t q = (s.len + 3) / 4;
-    const int64_t e0 = wave * q, e1 = e0 + q < s.len ? e0 + q : s.len;
-    for (int64_t g = sub; g * 64 < s.nvec; g += kStatBlocks) {
-      const int64_t v = g * 64 + lane;
+    const int r = tid % kStatRows, sg = tid / kStatRows;
+    const int64_t q = (s.len + kStatSegs - 1) / kStatSegs;
+    const int64_t e0 = sg * q, e1 = e0 + q < s.len ? e0 + q : s.len;
+    for (int64_t g = sub; g * kStatRows < s.nvec; g += kStatBlocks) {
+      const int64_t v = g * kStatRows + r;
       double n = 0.0, s1 = 0.0, s2 = 0.0;
       if (v < s.nvec) vec_logsums(X, s, v, e0, e1, 1, &n, &s1, &s2);
-      ws[0][wave][lane] = n;
-      ws[1][wave][lane] = s1;
-      ws[2][wave][lane] = s2;
+      ws[0][sg][r] = n;
+      ws[1][sg][r] = s1;
+      ws[2][sg][r] = s2;
       __syncthreads();
-      if (wave == 0 && v < s.nvec) {
-        double t[3];
+      if (tid < kStatRows && v < s.nvec) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < kStatSegs; ++j)
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          t[k] = ((ws[k][0][lane] + ws[k][1][lane]) + ws[k][2][lane]) + ws[k][3][lane];
+          for (int k = 0; k < 3; ++k) t[k] += ws[k][j][tid];
         if (t[0] >= 2.0) {
           W += t[2] - t[1] * t[1] / t[0];
           D += t[0] - 1.0;
