@@ -513,6 +513,25 @@ def test_fused_nonfinite_rows_and_columns_and_padding():
     assert _bits_equal(C[np.ix_(rows, cols)], ref.gemm(A[rows], B[:, cols], 14)["C"])
 
 
+def test_fused_flagged_rows_with_infinities_and_overflowing_norms():
+    """Rows of A flagged by a non-finite squared norm -- an infinite entry,
+    entries whose squares overflow, a NaN beside an infinity -- give NaN rows
+    through the fused kernel too (their entries converted through the clamp
+    to well-defined integers), and every other entry equals the separate
+    kernels and the oracle bit for bit."""
+    A, B = inputs.problem(130, 64, 300, 1.0, seed=73)
+    A[3, 5] = -np.inf
+    A[20, :] = 1e200 * np.sign(A[20, :])
+    A[40, 7] = np.inf
+    A[40, 8] = np.nan
+    C = _gpu_dgemm(A, B, 14)
+    for i in (3, 20, 40):
+        assert np.isnan(C[i]).all()
+    assert _bits_equal(C, _forced_unfused(A, B, 14))
+    rows = [i for i in range(130) if i not in (3, 20, 40)]
+    assert _bits_equal(C[rows], ref.gemm(A[rows], B, 14)["C"])
+
+
 def test_fused_sgemm_matches_unfused():
     A, B = inputs.problem(150, 48, 260, 1.0, seed=72)
     A32, B32 = A.astype(np.float32), B.astype(np.float32)
