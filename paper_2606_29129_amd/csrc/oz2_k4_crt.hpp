@@ -207,31 +207,37 @@ OZ2_HD double crt_unscale(const double (&acc)[S], const ModTable& T, int32_t E) 
   return neg ? -res : res;
 }
 
-// Two waves per 32 x 32 block: wave h (0 or 1) of the block takes the 8
-// accumulator-order entries 8h .. 8h + 7 of each lane, i.e. rows 16h ..
-// 16h + 15 of the block (all 32 columns), 8 of the 16 bytes each plane holds
-// per lane.  (Twice the waves of one wave per block: at small sizes the grid
-// is otherwise a single wave per SIMD whose plane loads and reconstruction
-// run back to back.)  The results go through a per-wave LDS tile so that
-// each store instruction writes four 16-entry column segments of C.
+// WPB (2 or 4) waves per 32 x 32 block: wave h of the block takes the
+// R = 16 / WPB accumulator-order entries R h .. R h + R - 1 of each lane,
+// i.e. rows (32 / WPB) h .. (32 / WPB)(h + 1) - 1 of the block (all 32
+// columns), R of the 16 bytes each plane holds per lane.  (More waves than
+// one per block: at small sizes the grid is otherwise one wave or less per
+// SIMD whose plane loads and reconstruction run back to back; two per block
+// in general, four for small outputs.)  The results go through a per-wave
+// LDS tile so that each store instruction writes column segments of
+// 32 / WPB entries.
 constexpr int kK4WavesPerBlock = 2;
+constexpr int kK4WavesPerBlockSmall = 4;
 
-template <int S, typename TO>
+template <int S, typename TO, int WPB = kK4WavesPerBlock>
 __device__ __forceinline__ void k4_crt_body(
     const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
     const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc, int64_t bx) {
-  __shared__ TO tile[4][16][33];
+  static_assert(WPB == 2 || WPB == 4, "waves per block");
+  constexpr int RPW = 32 / WPB;             // rows of the block per wave
+  __shared__ TO tile[4][RPW][33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t Mb = Mp / 32, Nb = Np / 32;
   const int64_t wid = bx * 4 + wave;
-  const int64_t blk = wid / kK4WavesPerBlock;
-  const int h = (int)(wid % kK4WavesPerBlock);
+  const int64_t blk = wid / WPB;
+  const int h = (int)(wid % WPB);
   const int64_t mb_used = (m + 31) / 32;
   const int64_t nb_used = (n + 31) / 32;
   if (blk >= mb_used * nb_used) return;  // whole wave: the tile is per wave
   const int64_t bi = blk % mb_used, bj = blk / mb_used;
-  const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16 + 8 * h;
+  constexpr int R = 16 / WPB, RW = R / 4, PF = 4;
+  const uint8_t* src = U + (bj * Mb + bi) * 1024 + lane * 16 + R * h;
   const int64_t plane = Nb * Mb * 1024;
   const int lc = acc_col(lane);
   const int64_t col = bj * 32 + lc;
@@ -243,7 +249,6 @@ __device__ __forceinline__ void k4_crt_body(
   // plane indices are clamped to N - 1 (a repeated, in-bounds load) rather
   // than skipped: with a fixed number of loads in flight the waits before
   // the current group's accumulation leave the next group's loads pending.
-  constexpr int R = 8, RW = 2, PF = 4;
   // The row exponents of this lane's outputs, loaded up front.
   int32_t er[R];
 #pragma unroll
@@ -257,9 +262,13 @@ __device__ __forceinline__ void k4_crt_body(
 #pragma unroll
     for (int s = 0; s < S; ++s) acc[r][s] = 0.0;
   auto load_plane = [&](int t, uint32_t (&ws)[RW]) {
-    const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane);
-    ws[0] = w.x;
-    ws[1] = w.y;
+    if constexpr (RW == 2) {
+      const uint2 w = *reinterpret_cast<const uint2*>(src + (int64_t)t * plane);
+      ws[0] = w.x;
+      ws[1] = w.y;
+    } else {
+      ws[0] = *reinterpret_cast<const uint32_t*>(src + (int64_t)t * plane);
+    }
   };
   auto accumulate = [&](int t, const uint32_t (&ws)[RW]) {
     double wt[S];
@@ -289,7 +298,7 @@ __device__ __forceinline__ void k4_crt_body(
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int lr = acc_row(R * h + r, lane);     // 16 h .. 16 h + 15
+    const int lr = acc_row(R * h + r, lane);     // RPW h .. RPW h + RPW - 1
     const int64_t row = bi * 32 + lr;
     double v = 0.0;
     if (row < m && col < n) {
@@ -304,29 +313,29 @@ __device__ __forceinline__ void k4_crt_body(
         else v = crt_unscale<S, 24, -149>(a, T, e + f);
       }
     }
-    tile[wave][lr - 16 * h][lc] = (TO)v;
+    tile[wave][lr - RPW * h][lc] = (TO)v;
   }
   // LDS operations of one wave complete in order; the fence keeps the
   // compiler from moving the reads above the writes.
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int orow = lane & 15;
-  const int64_t row = bi * 32 + 16 * h + orow;
+  const int orow = lane % RPW;
+  const int64_t row = bi * 32 + RPW * h + orow;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int oc = 4 * i + (lane >> 4);
+  for (int i = 0; i < RPW / 2; ++i) {
+    const int oc = (64 / RPW) * i + lane / RPW;
     const int64_t c = bj * 32 + oc;
     if (row < m && c < n) C[row + c * ldc] = tile[wave][orow][oc];
   }
 }
 
-template <int S, typename TO>
+template <int S, typename TO, int WPB = kK4WavesPerBlock>
 __global__ __launch_bounds__(256) void k4_crt(
     const uint8_t* __restrict__ U, const int32_t* __restrict__ eA,
     const int32_t* __restrict__ eB, const ModTable* __restrict__ tab, int N,
     int64_t m, int64_t n, int64_t Mp, int64_t Np, TO* __restrict__ C, int64_t ldc) {
-  k4_crt_body<S, TO>(U, eA, eB, tab, N, m, n, Mp, Np, C, ldc, blockIdx.x);
+  k4_crt_body<S, TO, WPB>(U, eA, eB, tab, N, m, n, Mp, Np, C, ldc, blockIdx.x);
 }
 
 // C = 0 (k = 0).

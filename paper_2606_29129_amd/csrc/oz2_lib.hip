@@ -333,10 +333,20 @@ void launch_gemm_blocked(int cfg, const int8_t* RA, const int8_t* RB, uint8_t* U
 template <int S, typename TO>
 void launch_crt(const Layout& L, char* ws, const ModTable* tab, int N, int64_t m, int64_t n,
                 TO* C, int64_t ldc) {
-  int64_t waves = ((m + 31) / 32) * ((n + 31) / 32) * kK4WavesPerBlock;
-  k4_crt<S, TO><<<(unsigned)((waves + 3) / 4), 256, 0, g_stream>>>(
-      (const uint8_t*)(ws + L.U), (const int32_t*)(ws + L.eA), (const int32_t*)(ws + L.eB),
-      tab, N, m, n, L.Mp, L.Np, C, ldc);
+  const int64_t blocks = ((m + 31) / 32) * ((n + 31) / 32);
+  // four waves per 32 x 32 block when two would leave fewer than four
+  // waves per SIMD (1024 SIMDs)
+  if (blocks * kK4WavesPerBlock < 4 * 1024) {
+    const int64_t waves = blocks * kK4WavesPerBlockSmall;
+    k4_crt<S, TO, kK4WavesPerBlockSmall><<<(unsigned)((waves + 3) / 4), 256, 0, g_stream>>>(
+        (const uint8_t*)(ws + L.U), (const int32_t*)(ws + L.eA), (const int32_t*)(ws + L.eB),
+        tab, N, m, n, L.Mp, L.Np, C, ldc);
+  } else {
+    const int64_t waves = blocks * kK4WavesPerBlock;
+    k4_crt<S, TO><<<(unsigned)((waves + 3) / 4), 256, 0, g_stream>>>(
+        (const uint8_t*)(ws + L.U), (const int32_t*)(ws + L.eA), (const int32_t*)(ws + L.eB),
+        tab, N, m, n, L.Mp, L.Np, C, ldc);
+  }
 }
 
 // fixed_ws: the device's `scratch` array as the workspace (no stage events,
