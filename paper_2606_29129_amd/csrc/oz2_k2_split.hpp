@@ -127,44 +127,64 @@ __device__ __forceinline__ void store_packed(int8_t* dst, const uint32_t (&w)[EP
 }
 
 // Strided vectors (rows of column-major A): entry h of vector v at
-// X[v + h ld].  A block of 256 lanes covers VB vectors x (256 / VB) * 16
+// X[v + h ld].  A block of 256 lanes covers VB vectors x (256 / VB) * EPS
 // entries: lane = (vector tid % VB, entry group tid / VB), so each load
 // instruction reads VB consecutive entries of a column per group; every lane
-// converts 16 entries.  Per plane the block's residue bytes are staged in LDS
-// (rows padded by 16 bytes: conflict-free 16-byte writes; two buffers, one
-// barrier per plane) and written out as whole rows of (256 / VB) * 16 bytes.
+// converts EPS entries (16; 8 for small problems, twice the blocks).  Per
+// plane the block's residue bytes are staged in LDS (rows padded by one
+// group: conflict-free writes; two buffers, one barrier per plane) and
+// written out as whole rows of (256 / VB) * EPS bytes.
 constexpr int kK2VB = 32;                       // vectors per strided block
-constexpr int kK2HB = (256 / kK2VB) * 16;       // entries per strided block
+constexpr int kK2HB = (256 / kK2VB) * 16;       // entries per strided block (EPS 16)
+constexpr int kK2HBSmall = (256 / kK2VB) * 8;   // (EPS 8)
 
-template <typename T, int LIMBS, int VB = kK2VB>
+template <int EPS>
+struct K2Chunk;
+template <>
+struct K2Chunk<16> {
+  typedef uint4 type;
+  static __device__ __forceinline__ uint4 make(const uint32_t (&w)[4]) {
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+template <>
+struct K2Chunk<8> {
+  typedef uint2 type;
+  static __device__ __forceinline__ uint2 make(const uint32_t (&w)[2]) {
+    return make_uint2(w[0], w[1]);
+  }
+};
+
+template <typename T, int LIMBS, int VB = kK2VB, int EPS = 16>
 __device__ __forceinline__ void k2_split_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
     int8_t* __restrict__ R, int64_t Vp, int64_t Kp, int64_t bx, int64_t by) {
-  constexpr int G = 256 / VB, HB = G * 16;
-  static_assert(VB * G == 256 && (VB * HB / 16) == 256, "one write-out pass");
-  __shared__ uint4 stage[2][VB][G + 1];
+  constexpr int G = 256 / VB, HB = G * EPS;
+  static_assert(VB * G == 256 && (VB * HB / EPS) == 256, "one write-out pass");
+  typedef typename K2Chunk<EPS>::type Chunk;
+  __shared__ Chunk stage[2][VB][G + 1];
   const int vl = threadIdx.x % VB, g = threadIdx.x / VB;
   const int64_t v0 = bx * VB, v = v0 + vl;
-  const int64_t h0 = by * HB + g * 16;
+  const int64_t h0 = by * HB + g * EPS;
   const int32_t ev = v < nvec ? e[v] : 0;
-  Limbs<LIMBS> L[16];
+  Limbs<LIMBS> L[EPS];
   {
-    double a[16];
+    double a[EPS];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
+    for (int i = 0; i < EPS; ++i)
       a[i] = (v < nvec && h0 + i < k) ? nt_load(X + v + (h0 + i) * ld) : 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) L[i] = make_limbs<LIMBS>(a[i], ev);
+    for (int i = 0; i < EPS; ++i) L[i] = make_limbs<LIMBS>(a[i], ev);
   }
   const int64_t plane = Vp * Kp;
   const int orow = threadIdx.x / G, ochunk = threadIdx.x % G;  // write-out mapping
-  int8_t* out = R + (v0 + orow) * Kp + by * HB + ochunk * 16;
+  int8_t* out = R + (v0 + orow) * Kp + by * HB + ochunk * EPS;
   for (int t = 0; t < N; ++t) {
     const int sb = t & 1;
-    uint32_t w[4];
-    pack_residues<LIMBS, 16>(L, t, tab, w);
-    stage[sb][vl][g] = make_uint4(w[0], w[1], w[2], w[3]);
+    uint32_t w[EPS / 4];
+    pack_residues<LIMBS, EPS>(L, t, tab, w);
+    stage[sb][vl][g] = K2Chunk<EPS>::make(w);
     __syncthreads();
     nt_store(out + (int64_t)t * plane, stage[sb][orow][ochunk]);
   }
@@ -223,7 +243,7 @@ __global__ __launch_bounds__(256) void k2_split_contig(
 // Both operands in one launch: blocks [0, nA) run the strided kernel's
 // blocks for A (nA = gAx x Kp / kK2HB, gAx = Mp / kK2VB), the others the
 // contiguous kernel's blocks for B.
-template <typename T, int LIMBS>
+template <typename T, int LIMBS, int EPS = 16>
 __global__ __launch_bounds__(256) void k2_split_ab(
     const T* __restrict__ A, int64_t lda, int64_t m, const int32_t* __restrict__ eA,
     int8_t* __restrict__ RA, int64_t Mp, const T* __restrict__ B, int64_t ldb, int64_t n,
@@ -231,7 +251,8 @@ __global__ __launch_bounds__(256) void k2_split_ab(
     const ModTable* __restrict__ tab, int N, int64_t Kp, int64_t gAx, int64_t nA) {
   const int64_t b = blockIdx.x;
   if (b < nA)
-    k2_split_strided_body<T, LIMBS>(A, lda, m, k, eA, tab, N, RA, Mp, Kp, b % gAx, b / gAx);
+    k2_split_strided_body<T, LIMBS, kK2VB, EPS>(A, lda, m, k, eA, tab, N, RA, Mp, Kp, b % gAx,
+                                                b / gAx);
   else
     k2_split_contig_body<T, LIMBS>(B, ldb, n, k, eB, tab, N, RB, Np, Kp, b - nA);
 }

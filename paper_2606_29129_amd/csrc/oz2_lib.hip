@@ -289,6 +289,14 @@ void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, i
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
   const int64_t gAx = L.Mp / kK2VB, nA = gAx * (L.Kp / kK2HB);
   const int64_t nB = (L.Np * (L.Kp / kK2EPT) + 255) / 256;
+  if (nA + nB < 4 * 256) {
+    // small problems: 8 entries of A per lane, twice the blocks for A
+    const int64_t nA8 = gAx * (L.Kp / kK2HBSmall);
+    k2_split_ab<T, LIMBS, 8><<<(unsigned)(nA8 + nB), 256, 0, g_stream>>>(
+        A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
+        (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA8);
+    return;
+  }
   k2_split_ab<T, LIMBS><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
       A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
       (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA);
