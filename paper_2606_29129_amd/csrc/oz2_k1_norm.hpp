@@ -44,7 +44,7 @@ OZ2_HD double norm_entry(double a) {
 // once and does not fit the caches).
 // RESC: the exact mode's second pass, only for vectors whose exponent is
 // kExpRescale (esel), summing the scaled-down entries.
-template <typename T, bool RESC = false>
+template <typename T, bool RESC = false, bool NT = true>
 __device__ __forceinline__ void k1_partials_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k, int64_t nchunks,
     double* __restrict__ part, double* __restrict__ pmax, int64_t bx, int64_t by,
@@ -64,7 +64,8 @@ __device__ __forceinline__ void k1_partials_strided_body(
       double a[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i)
-        a[i] = norm_entry<RESC>((double)__builtin_nontemporal_load(p + (int64_t)(b + i) * ld));
+        a[i] = norm_entry<RESC>(NT ? (double)__builtin_nontemporal_load(p + (int64_t)(b + i) * ld)
+                                   : (double)p[(int64_t)(b + i) * ld]);
       s = ru_add_squares(s, a);
 #pragma unroll
       for (int i = 0; i < 16; ++i) mx = fmax(mx, fabs(a[i]));
@@ -276,7 +277,9 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 // [0, nA) take the rows of A (nA = gAx x ceil(nchunks / 4) blocks of the
 // strided kernel's grid), the others the columns of B.  Block 0 also clears
 // the status word, which only later launches read or write.
-template <typename T>
+// NT = false (small problems): ordinary loads, so that the operands stay in
+// the caches for the conversion kernel.
+template <typename T, bool NT = true>
 __global__ __launch_bounds__(256) void k1_partials_ab(
     const T* __restrict__ A, int64_t lda, int64_t m, const T* __restrict__ B, int64_t ldb,
     int64_t n, int64_t k, int64_t nchunks, double* __restrict__ partA,
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(256) void k1_partials_ab(
   const int64_t b = blockIdx.x;
   if (b == 0 && threadIdx.x == 0) status[0] = 0;
   if (b < nA)
-    k1_partials_strided_body<T>(A, lda, m, k, nchunks, partA, maxA, b % gAx, b / gAx);
+    k1_partials_strided_body<T, false, NT>(A, lda, m, k, nchunks, partA, maxA, b % gAx, b / gAx);
   else
     k1_partials_contig_body<T>(B, ldb, n, k, nchunks, partB, maxB, b - nA);
 }

@@ -119,11 +119,25 @@ __device__ __forceinline__ double nt_load(const T* p) {
   return (double)__builtin_nontemporal_load(p);
 }
 
-template <int EPT>
+// NT = false (small problems): ordinary loads and stores, so that the
+// operands stay in the caches for the next kernel that reads them and the
+// residue planes for the GEMM.
+template <bool NT, typename V>
+__device__ __forceinline__ void store_out(int8_t* dst, V v) {
+  if constexpr (NT) nt_store(dst, v);
+  else *reinterpret_cast<V*>(dst) = v;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ double load_in(const T* p) {
+  if constexpr (NT) return nt_load(p);
+  else return (double)*p;
+}
+
+template <int EPT, bool NT = true>
 __device__ __forceinline__ void store_packed(int8_t* dst, const uint32_t (&w)[EPT / 4]) {
-  if constexpr (EPT == 4) nt_store(dst, w[0]);
-  else if constexpr (EPT == 8) nt_store(dst, make_uint2(w[0], w[1]));
-  else nt_store(dst, make_uint4(w[0], w[1], w[2], w[3]));
+  if constexpr (EPT == 4) store_out<NT>(dst, w[0]);
+  else if constexpr (EPT == 8) store_out<NT>(dst, make_uint2(w[0], w[1]));
+  else store_out<NT>(dst, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 // Strided vectors (rows of column-major A): entry h of vector v at
@@ -155,7 +169,7 @@ struct K2Chunk<8> {
   }
 };
 
-template <typename T, int LIMBS, int VB = kK2VB, int EPS = 16>
+template <typename T, int LIMBS, int VB = kK2VB, int EPS = 16, bool NT = true>
 __device__ __forceinline__ void k2_split_strided_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
@@ -173,7 +187,7 @@ __device__ __forceinline__ void k2_split_strided_body(
     double a[EPS];
 #pragma unroll
     for (int i = 0; i < EPS; ++i)
-      a[i] = (v < nvec && h0 + i < k) ? nt_load(X + v + (h0 + i) * ld) : 0.0;
+      a[i] = (v < nvec && h0 + i < k) ? load_in<NT>(X + v + (h0 + i) * ld) : 0.0;
 #pragma unroll
     for (int i = 0; i < EPS; ++i) L[i] = make_limbs<LIMBS>(a[i], ev);
   }
@@ -186,7 +200,7 @@ __device__ __forceinline__ void k2_split_strided_body(
     pack_residues<LIMBS, EPS>(L, t, tab, w);
     stage[sb][vl][g] = K2Chunk<EPS>::make(w);
     __syncthreads();
-    nt_store(out + (int64_t)t * plane, stage[sb][orow][ochunk]);
+    store_out<NT>(out + (int64_t)t * plane, stage[sb][orow][ochunk]);
   }
 }
 
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256) void k2_split_strided(
 // neighbouring lanes read and write neighbouring groups, EPT-byte stores.
 constexpr int kK2EPT = 8;
 
-template <typename T, int LIMBS, int EPT = kK2EPT>
+template <typename T, int LIMBS, int EPT = kK2EPT, bool NT = true>
 __device__ __forceinline__ void k2_split_contig_body(
     const T* __restrict__ X, int64_t ld, int64_t nvec, int64_t k,
     const int32_t* __restrict__ e, const ModTable* __restrict__ tab, int N,
@@ -228,7 +242,7 @@ __device__ __forceinline__ void k2_split_contig_body(
   for (int t = 0; t < N; ++t) {
     uint32_t w[EPT / 4];
     pack_residues<LIMBS, EPT>(L, t, tab, w);
-    store_packed<EPT>(out + (int64_t)t * plane, w);
+    store_packed<EPT, NT>(out + (int64_t)t * plane, w);
   }
 }
 
@@ -243,7 +257,7 @@ __global__ __launch_bounds__(256) void k2_split_contig(
 // Both operands in one launch: blocks [0, nA) run the strided kernel's
 // blocks for A (nA = gAx x Kp / kK2HB, gAx = Mp / kK2VB), the others the
 // contiguous kernel's blocks for B.
-template <typename T, int LIMBS, int EPS = 16>
+template <typename T, int LIMBS, int EPS = 16, bool NT = true>
 __global__ __launch_bounds__(256) void k2_split_ab(
     const T* __restrict__ A, int64_t lda, int64_t m, const int32_t* __restrict__ eA,
     int8_t* __restrict__ RA, int64_t Mp, const T* __restrict__ B, int64_t ldb, int64_t n,
@@ -251,10 +265,10 @@ __global__ __launch_bounds__(256) void k2_split_ab(
     const ModTable* __restrict__ tab, int N, int64_t Kp, int64_t gAx, int64_t nA) {
   const int64_t b = blockIdx.x;
   if (b < nA)
-    k2_split_strided_body<T, LIMBS, kK2VB, EPS>(A, lda, m, k, eA, tab, N, RA, Mp, Kp, b % gAx,
-                                                b / gAx);
+    k2_split_strided_body<T, LIMBS, kK2VB, EPS, NT>(A, lda, m, k, eA, tab, N, RA, Mp, Kp,
+                                                    b % gAx, b / gAx);
   else
-    k2_split_contig_body<T, LIMBS>(B, ldb, n, k, eB, tab, N, RB, Np, Kp, b - nA);
+    k2_split_contig_body<T, LIMBS, kK2EPT, NT>(B, ldb, n, k, eB, tab, N, RB, Np, Kp, b - nA);
 }
 
 // Accurate mode: abar = ceil(|a| 2^e') in [0, 64] (Section 2.3), one int8

@@ -284,15 +284,24 @@ struct Debug {
   int8_t *RA, *RB;
 };
 
+// Small problems (K2 would launch fewer than 1024 blocks): K2 takes 8 entries
+// of A per lane (twice the blocks for A), and K1 and K2 use ordinary loads
+// and stores, so that the operands and residue planes stay in the caches for
+// the next kernel.
+bool small_problem(const Layout& L) {
+  const int64_t nA = (L.Mp / kK2VB) * (L.Kp / kK2HB);
+  const int64_t nB = (L.Np * (L.Kp / kK2EPT) + 255) / 256;
+  return nA + nB < 4 * 256;
+}
+
 template <typename T, int LIMBS>
 void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, int64_t n,
                   int64_t k, const Layout& L, char* ws, const ModTable* tab, int N) {
   const int64_t gAx = L.Mp / kK2VB, nA = gAx * (L.Kp / kK2HB);
   const int64_t nB = (L.Np * (L.Kp / kK2EPT) + 255) / 256;
-  if (nA + nB < 4 * 256) {
-    // small problems: 8 entries of A per lane, twice the blocks for A
+  if (small_problem(L)) {
     const int64_t nA8 = gAx * (L.Kp / kK2HBSmall);
-    k2_split_ab<T, LIMBS, 8><<<(unsigned)(nA8 + nB), 256, 0, g_stream>>>(
+    k2_split_ab<T, LIMBS, 8, false><<<(unsigned)(nA8 + nB), 256, 0, g_stream>>>(
         A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
         (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA8);
     return;
@@ -414,9 +423,14 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
     {
       // both operands' partial sums (and the status word's reset) in one launch
       const int64_t nA = (int64_t)gA.x * gA.y, nB = (work + 255) / 256;
-      k1_partials_ab<T><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
-          A, lda, m, B, ldb, n, k, L.nch, (double*)(ws + L.partA), pmA, (double*)(ws + L.partB),
-          pmB, (int64_t)gA.x, nA, (int*)(ws + L.status));
+      if (small_problem(L))
+        k1_partials_ab<T, false><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
+            A, lda, m, B, ldb, n, k, L.nch, (double*)(ws + L.partA), pmA,
+            (double*)(ws + L.partB), pmB, (int64_t)gA.x, nA, (int*)(ws + L.status));
+      else
+        k1_partials_ab<T><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
+            A, lda, m, B, ldb, n, k, L.nch, (double*)(ws + L.partA), pmA,
+            (double*)(ws + L.partB), pmB, (int64_t)gA.x, nA, (int*)(ws + L.status));
     }
     if (mode != OZ2_MODE_ACCURATE) {
       const int64_t fA = (m + 255) / 256, fB = (n + 255) / 256;
