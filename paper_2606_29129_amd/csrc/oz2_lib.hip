@@ -285,13 +285,16 @@ struct Debug {
 };
 
 // Small problems (K2 would launch fewer than 1024 blocks): K2 takes 8 entries
-// of A per lane (twice the blocks for A), and K1 and K2 use ordinary loads
-// and stores, so that the operands and residue planes stay in the caches for
-// the next kernel.
+// of A per lane (twice the blocks for A).  Residue planes that fit in half
+// the MALL (128 MiB): K1 and K2 use ordinary loads and stores, so that the
+// operands stay in the caches for K2 and the planes for the GEMM.
 bool small_problem(const Layout& L) {
   const int64_t nA = (L.Mp / kK2VB) * (L.Kp / kK2HB);
   const int64_t nB = (L.Np * (L.Kp / kK2EPT) + 255) / 256;
   return nA + nB < 4 * 256;
+}
+bool cache_resident(const Layout& L, int N) {
+  return (int64_t)N * (L.Mp + L.Np) * L.Kp <= (int64_t(128) << 20);
 }
 
 template <typename T, int LIMBS>
@@ -304,6 +307,12 @@ void launch_split(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t m, i
     k2_split_ab<T, LIMBS, 8, false><<<(unsigned)(nA8 + nB), 256, 0, g_stream>>>(
         A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
         (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA8);
+    return;
+  }
+  if (cache_resident(L, N)) {
+    k2_split_ab<T, LIMBS, 16, false><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
+        A, lda, m, (const int32_t*)(ws + L.eA), (int8_t*)(ws + L.RA), L.Mp, B, ldb, n,
+        (const int32_t*)(ws + L.eB), (int8_t*)(ws + L.RB), L.Np, k, tab, N, L.Kp, gAx, nA);
     return;
   }
   k2_split_ab<T, LIMBS><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
@@ -423,7 +432,7 @@ int run_gemm(int64_t m, int64_t n, int64_t k, const T* A, int64_t lda, const T* 
     {
       // both operands' partial sums (and the status word's reset) in one launch
       const int64_t nA = (int64_t)gA.x * gA.y, nB = (work + 255) / 256;
-      if (small_problem(L))
+      if (small_problem(L) || cache_resident(L, N))
         k1_partials_ab<T, false><<<(unsigned)(nA + nB), 256, 0, g_stream>>>(
             A, lda, m, B, ldb, n, k, L.nch, (double*)(ws + L.partA), pmA,
             (double*)(ws + L.partB), pmB, (int64_t)gA.x, nA, (int*)(ws + L.status));
