@@ -81,17 +81,15 @@ constexpr int kBatchLimbs = 2;
 // Stages with a per-problem block count.
 enum BatchStage { kB_K1A = 0, kB_K1B, kB_FOLDA, kB_FOLDB, kB_K2A, kB_K2B, kB_K4, kB_NSTAGES };
 
-// One instantiation per stage, so that each gets the register budget (and
-// occupancy) of its own body.
-// A block finds its problem in a host-built table (one load) and its
-// position inside the problem from the stage's block prefix sums.
+// Block b of a stage (b counted from the stage's first block) finds its
+// problem in a host-built table (one load) and its position inside the
+// problem from the stage's block prefix sums.
 template <int STAGE>
-__global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ probs,
-                                                const int64_t* __restrict__ prefix,
-                                                const uint16_t* __restrict__ owner, int batch,
-                                                int* __restrict__ status) {
+__device__ __forceinline__ void kb_stage_body(const BatchProb* __restrict__ probs,
+                                              const int64_t* __restrict__ prefix,
+                                              const uint16_t* __restrict__ owner, int batch,
+                                              int* __restrict__ status, int64_t b) {
   const int64_t* pre = prefix + (int64_t)STAGE * (batch + 1);
-  const int64_t b = blockIdx.x;
   const int p = owner[b];
   const int64_t local = b - pre[p];
   const BatchProbDev& P = reinterpret_cast<const BatchProbDev*>(probs)[p];
@@ -137,6 +135,33 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
                              (double*)P.C, P.ldc, local);
       break;
   }
+}
+
+// One stage per launch (one instantiation per stage, so that each gets the
+// register budget and occupancy of its own body).
+template <int STAGE>
+__global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ probs,
+                                                const int64_t* __restrict__ prefix,
+                                                const uint16_t* __restrict__ owner, int batch,
+                                                int* __restrict__ status) {
+  kb_stage_body<STAGE>(probs, prefix, owner, batch, status, blockIdx.x);
+}
+
+// The A and the B half of one step (two independent stages) in one launch:
+// blocks [0, nfirst) run stage S1, the others stage S2, whose owner entries
+// follow S1's in the owner table.  The halves overlap instead of the second
+// waiting for the first one's last blocks.
+template <int S1, int S2>
+__global__ __launch_bounds__(256) void kb_stage_pair(const BatchProb* __restrict__ probs,
+                                                     const int64_t* __restrict__ prefix,
+                                                     const uint16_t* __restrict__ owner,
+                                                     int batch, int64_t nfirst,
+                                                     int* __restrict__ status) {
+  const int64_t b = blockIdx.x;
+  if (b < nfirst)
+    kb_stage_body<S1>(probs, prefix, owner, batch, status, b);
+  else
+    kb_stage_body<S2>(probs, prefix, owner + nfirst, batch, status, b - nfirst);
 }
 
 // Work item: problem, plane, tile row, tile column (16 bits each).

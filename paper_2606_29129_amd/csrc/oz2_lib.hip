@@ -859,6 +859,9 @@ int plan_batch(int batch, const oz2_problem* P, int mode, size_t tune_ops, Batch
     pl->blocks[st] = acc;
     if (acc > INT32_MAX) return OZ2_ERR_TOO_LARGE;
   }
+  // the A and B halves of a step share one launch
+  for (int st : {kB_K1A, kB_FOLDA, kB_K2A})
+    if (pl->blocks[st] + pl->blocks[st + 1] > INT32_MAX) return OZ2_ERR_TOO_LARGE;
   pl->total_blocks = 0;
   for (int st = 0; st < kB_NSTAGES; ++st) {
     pl->owner_off[st] = pl->total_blocks;
@@ -951,18 +954,21 @@ void enqueue_batch(hipStream_t s, const BatchPlan& pl, char* ws, int64_t gemm_gr
   if (pl.blocks[ST] > 0)                                                                \
     kb_stage<ST><<<(unsigned)pl.blocks[ST], 256, 0, s>>>(d_probs, d_prefix,               \
                                                        d_owner + pl.owner_off[ST], na, d_status);
-  OZ2_STAGE(kB_K1A)
-  OZ2_STAGE(kB_K1B)
-  OZ2_STAGE(kB_FOLDA)
-  OZ2_STAGE(kB_FOLDB)
+#define OZ2_STAGE_PAIR(S1, S2)                                                            \
+  static_assert(S2 == S1 + 1, "owner entries of S2 follow S1's");                       \
+  if (pl.blocks[S1] + pl.blocks[S2] > 0)                                                \
+    kb_stage_pair<S1, S2><<<(unsigned)(pl.blocks[S1] + pl.blocks[S2]), 256, 0, s>>>(       \
+        d_probs, d_prefix, d_owner + pl.owner_off[S1], na, pl.blocks[S1], d_status);
+  OZ2_STAGE_PAIR(kB_K1A, kB_K1B)
+  OZ2_STAGE_PAIR(kB_FOLDA, kB_FOLDB)
   if (clk) clk->mark(1);
-  OZ2_STAGE(kB_K2A)
-  OZ2_STAGE(kB_K2B)
+  OZ2_STAGE_PAIR(kB_K2A, kB_K2B)
   if (clk) clk->mark(2);
   kb_gemm<<<(unsigned)gemm_grid, 256, 0, s>>>(d_probs, (const WorkItem*)(ws + pl.off_items),
                                               (int)pl.nitems);
   if (clk) clk->mark(3);
   OZ2_STAGE(kB_K4)
+#undef OZ2_STAGE_PAIR
 #undef OZ2_STAGE
   if (clk) {
     clk->mark(4);
