@@ -184,17 +184,7 @@ __device__ __forceinline__ void tile_epilogue(
   }
   const int64_t Nb = Np / 32;
   const bool is256 = (t == 0);
-  // Symmetric residue r = c - q p, q = round(c / p), for odd p in two fmas
-  // and an integer add: fma(c, 1/p, 1.5 2^52) = 1.5 2^52 + q (the product is
-  // exact inside the fma and the sum's unit is 1; c / p lies at least 1/(2p)
-  // from a half-integer and |c (1/p) - c / p| < 2^-22 / p, so q is the
-  // nearest integer to c / p); fma(that, -p, 1.5 2^52 (p + 1)) has the exact
-  // value 1.5 2^52 - q p (|q p| < 2^31), whose low word is -q p in two's
-  // complement, so c plus that word is r, |r| <= (p - 1) / 2.  One
-  // instruction fewer per entry than rounding c / p to an integer and
-  // converting the remainder back.
   const double p = tab->p[t], ip = tab->inv_p[t];
-  const double kMagic = 0x1.8p52, magic_p1 = kMagic * (p + 1.0);  // both exact
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -209,9 +199,10 @@ __device__ __forceinline__ void tile_epilogue(
           if (is256) {
             u[e] = (uint32_t)c;                   // the low byte is kept
           } else {
-            const double tq = fma((double)c, ip, kMagic);   // 1.5 2^52 + q
-            const double nq = fma(tq, -p, magic_p1);        // 1.5 2^52 - q p, exact
-            u[e] = (uint32_t)c + (uint32_t)__double_as_longlong(nq);  // r; its byte is kept
+            // symmetric residue, |r| <= (p-1)/2 (one instruction fewer per
+            // entry than rounding c / p and converting the remainder back);
+            // its two's-complement byte is kept
+            u[e] = residue_sym_i32(c, p, ip);
           }
         }
         w[q] = pack_low_bytes(u[0], u[1], u[2], u[3]);

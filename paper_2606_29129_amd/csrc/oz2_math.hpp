@@ -58,6 +58,24 @@ OZ2_HD uint64_t f64_to_bits(double d) { return __builtin_bit_cast(uint64_t, d); 
 OZ2_HD float bits_to_f32(uint32_t u) { return __builtin_bit_cast(float, u); }
 OZ2_HD uint32_t f32_to_bits(float f) { return __builtin_bit_cast(uint32_t, f); }
 
+// The symmetric residue r = c - q p, q = round(c / p), of an integer c with
+// |c| < 2^31 for an odd modulus p < 256 (ip = 1/p rounded to nearest), as a
+// 32-bit two's complement word: two fmas and an integer add.
+// fma(c, ip, 1.5 2^52) = 1.5 2^52 + q: the product is exact inside the fma
+// and the sum's unit is 1; c / p lies at least 1/(2p) from a half-integer
+// while |c ip - c / p| < 2^-22 / p, so q is the integer nearest to c / p.
+// fma(1.5 2^52 + q, -p, 1.5 2^52 (p + 1)) has the exact value
+// 1.5 2^52 - q p (|q p| < 2^31 + p, inside the binade of 1.5 2^52, whose
+// unit is 1), whose low word is -q p in two's complement, so c plus that
+// word is r, |r| <= (p - 1) / 2.
+OZ2_HD uint32_t residue_sym_i32(int32_t c, double p, double ip) {
+  constexpr double kMagic = 0x1.8p52;
+  const double magic_p1 = kMagic * (p + 1.0);             // exact: 1.5 (p + 1) < 2^9
+  const double tq = fma((double)c, ip, kMagic);           // 1.5 2^52 + q
+  const double nq = fma(tq, -p, magic_p1);                // 1.5 2^52 - q p, exact
+  return (uint32_t)c + (uint32_t)f64_to_bits(nq);
+}
+
 // Next binary64 above a finite non-negative x (0 -> smallest subnormal).
 OZ2_HD double next_up_nonneg(double x) { return bits_to_f64(f64_to_bits(x) + 1); }
 
