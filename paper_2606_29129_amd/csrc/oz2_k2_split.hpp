@@ -11,10 +11,15 @@
 // y = sum_j x_j (2^(40 j) mod p).  The fast modes have |a'| < 2^79 (two
 // limbs, |x_1| < 2^39): |y| < 2^40 + 2^47; accurate mode has |a'| < 2^86
 // (three limbs): |y| < 2^40 + 2^48 + 2^14.  So y is exact in binary64, and
-// q = rint(y / p) found from y * RN(1/p) is exact as well: the estimate's
+// q = round(y / p) found from y RN(1/p) is exact as well: the estimate's
 // error, |y / p| 2^-52 < 2^-3 / p, stays below the 1 / (2p) distance of y / p
-// from a half-integer.  r = y - q p is exact: the symmetric residue, with no
-// correction step.
+// from a half-integer.  r = y - q p is the symmetric residue, with no
+// correction step.  It is formed around 1.5 2^52, where the unit is 1:
+// fma(y, RN(1/p), 1.5 2^52) = 1.5 2^52 + q (the product is exact inside the
+// fma); fma(1.5 2^52 + q, -p, 1.5 2^52 (p + 1)) = 1.5 2^52 - q p and adding y
+// gives 1.5 2^52 + r, both exact (every value is an integer in [2^52, 2^53));
+// the low word of that encoding is r in two's complement.  Two fmas and an
+// add, against a multiply, a rounding, an fma and a conversion.
 //
 // Output layout: plane t is a (Vp x Kp) int8 matrix, vector-major with the
 // k index contiguous (what the GEMM reads); padding rows and columns are 0.
@@ -51,8 +56,10 @@ OZ2_HD int residue_odd(const Limbs<LIMBS>& L, const double* pw, double p, double
   double y = L.x[0];
 #pragma unroll
   for (int j = 1; j < LIMBS; ++j) y = fma(L.x[j], pw[j], y);
-  double q = rint(y * inv_p);
-  return (int)fma(-q, p, y);
+  constexpr double kMagic = 0x1.8p52;
+  const double tq = fma(y, inv_p, kMagic);           // 1.5 2^52 + q
+  const double s = fma(tq, -p, kMagic * (p + 1.0));  // 1.5 2^52 - q p (exact)
+  return (int)(uint32_t)f64_to_bits(s + y);          // 1.5 2^52 + r: low word r
 }
 
 // a' = x_0 (mod 256) since 256 divides 2^40.  x_0 (|x_0| < 2^40) does not
