@@ -2,10 +2,11 @@
 // handful of launches (captured once into a HIP graph by the host side).
 //
 // Every problem keeps its own workspace regions and constants table (its own
-// N).  The element-wise stages run as one 1-D grid per kernel: a block reads
-// its problem from a host-built block-to-problem table, its place inside the
-// problem from a prefix sum of per-problem block counts, and runs the same
-// body as the single-problem kernel.  The INT8 GEMM runs as a persistent
+// N).  The element-wise stages run as 1-D grids over the whole batch (the A
+// and B halves of a step share one launch): a block reads its problem from
+// a host-built block-to-problem table, its place inside the problem from a
+// prefix sum of per-problem block counts, and runs the same body as the
+// single-problem kernel.  The INT8 GEMM runs as a persistent
 // kernel over a list of (problem, plane, tile) items sorted by decreasing k,
 // dealt out round-robin to the workgroups.
 #pragma once
