@@ -152,8 +152,14 @@ __global__ __launch_bounds__(256) void kb_stage(const BatchProb* __restrict__ pr
 // blocks [0, nfirst) run stage S1, the others stage S2, whose owner entries
 // follow S1's in the owner table.  The halves overlap instead of the second
 // waiting for the first one's last blocks.
+// Three blocks per CU: the norm pair's bodies keep a chunk's 64 loads in
+// flight (174 registers, two waves per SIMD); capped at 168 registers (a
+// few spilled) a third wave covers the others' waits on the batch's short
+// vectors, 0.59 -> 0.51 ms for the 256-problem batch (the plain path's
+// norm kernel, on long vectors, is slower so capped).  The other pairs'
+// times do not change.
 template <int S1, int S2>
-__global__ __launch_bounds__(256) void kb_stage_pair(const BatchProb* __restrict__ probs,
+__global__ __launch_bounds__(256, 3) void kb_stage_pair(const BatchProb* __restrict__ probs,
                                                      const int64_t* __restrict__ prefix,
                                                      const uint16_t* __restrict__ owner,
                                                      int batch, int64_t nfirst,
